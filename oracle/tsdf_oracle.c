@@ -1,0 +1,596 @@
+/*
+ * TSDF oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded CPU implementation of the TSDF-mapping path
+ * of FeatSense (Gaal et al., arXiv 2310.05766, Sec. VI "TSDF Map Generation").
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load it. It shares no code, header or constant with the GPU library.
+ *
+ * Build: gcc -O2 -ffp-contract=off -std=c11 -shared -fPIC (no fast-math), so
+ * every floating-point operation below is exactly the IEEE operation written.
+ *
+ * What is computed (paper Sec. VI, readings of the paper's gaps are listed
+ * with each function):
+ *   1. each scan point is transformed to the world frame in float64 and
+ *      rounded to global fixed point, 1/1024 of a voxel;
+ *   2. the ray from the sensor position p to the point x is traversed across
+ *      the truncation band around x (Sec. VI: voxels are filled while
+ *      traversing the ray from p to x);
+ *   3. per scan, each voxel keeps the smallest distance over all rays that
+ *      reach it (Sec. VI: the per-scan volume V takes the smallest distance
+ *      of all rays for each voxel);
+ *   4. the per-scan volume is averaged into the global volume G with the
+ *      weighted running average of Eq. (1) and the capped weight of Eq. (2);
+ *   5. the local map is a window over G that shifts after a movement
+ *      threshold; voxels leaving it are written to a store and voxels
+ *      entering it are loaded back (Sec. I, HATSDF's local-map shift, and the
+ *      ring-buffer swapping of Kintinuous cited in Sec. II).
+ *
+ * Parity pins for every function live in tests/ (closed forms, brute force,
+ * invariants); nothing here is checked against itself.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOMEM (-2)
+
+#define KEY_EMPTY UINT64_MAX
+#define CHUNK 64
+
+/* ------------------------------------------------------------------ */
+/* integer helpers                                                     */
+/* ------------------------------------------------------------------ */
+
+/* Rounded division n/d for d > 0, to nearest, ties away from zero. Used for
+ * every division of the method (the paper leaves rounding unspecified). */
+int64_t or_rdiv(int64_t n, int64_t d)
+{
+    int64_t a = n < 0 ? -n : n;
+    int64_t q = (2 * a + d) / (2 * d);
+    return n < 0 ? -q : q;
+}
+
+/* floor(sqrt(n)), exact for every 64-bit n: bit-by-bit square root. */
+uint64_t or_isqrt(uint64_t n)
+{
+    uint64_t res = 0;
+    uint64_t bit = (uint64_t)1 << 62;
+    while (bit > n) bit >>= 2;
+    while (bit != 0) {
+        if (n >= res + bit) {
+            n -= res + bit;
+            res = (res >> 1) + bit;
+        } else {
+            res >>= 1;
+        }
+        bit >>= 2;
+    }
+    return res;
+}
+
+/* floor(a / b) for b > 0 */
+static int64_t floor_div(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    if ((a % b != 0) && (a < 0)) q -= 1;
+    return q;
+}
+
+static int64_t floor_mod(int64_t a, int64_t b) { return a - floor_div(a, b) * b; }
+
+static __int128 floor_div128(__int128 a, __int128 b)
+{
+    __int128 q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) q -= 1;
+    return q;
+}
+
+/* ------------------------------------------------------------------ */
+/* step 1: world transform and quantisation                            */
+/* ------------------------------------------------------------------ */
+
+/* Point (x,y,z) in the sensor frame -> world coordinate row a of the row-major
+ * 4x4 world_T_sensor M, as one fixed chain of fused multiply-adds:
+ *   w_a = fma(M[a][0], x, fma(M[a][1], y, fma(M[a][2], z, M[a][3]))).
+ * Then q_a = round-half-even(w_a * scale), scale = 1024 / voxel_size.
+ * Returns 1 if the point is kept: finite coordinates and |q_a| < 2^30. */
+int or_quantise_point(const float p[3], const double M[16], double scale, int64_t q[3])
+{
+    if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) return 0;
+    double x = (double)p[0], y = (double)p[1], z = (double)p[2];
+    for (int a = 0; a < 3; ++a) {
+        double w = fma(M[4 * a + 0], x, fma(M[4 * a + 1], y, fma(M[4 * a + 2], z, M[4 * a + 3])));
+        double r = nearbyint(w * scale);
+        if (!(fabs(r) < 1073741824.0)) return 0;
+        q[a] = (int64_t)r;
+    }
+    return 1;
+}
+
+/* Sensor position: o_a = round-half-even(M[a][3] * scale). Returns 0 when the
+ * position is not representable (|o_a| >= 2^30 or non-finite). */
+int or_quantise_origin(const double M[16], double scale, int64_t o[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        double r = nearbyint(M[4 * a + 3] * scale);
+        if (!(fabs(r) < 1073741824.0)) return 0;
+        o[a] = (int64_t)r;
+    }
+    return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* step 2: the band around the scan point                               */
+/* ------------------------------------------------------------------ */
+
+/* D = q - o, r = isqrt(|D|^2), off = rdiv(tau*D, r), E = q + off and
+ * S = q - off, or S = o when the point is within tau of the sensor.
+ * Returns 0 for D = 0 (no ray). */
+int or_band(const int64_t q[3], const int64_t o[3], int64_t tau_u,
+            int64_t D[3], uint64_t *r_out, int64_t S[3], int64_t E[3])
+{
+    uint64_t dd = 0;
+    for (int a = 0; a < 3; ++a) {
+        D[a] = q[a] - o[a];
+        dd += (uint64_t)(D[a] * D[a]);
+    }
+    if (dd == 0) return 0;
+    uint64_t r = or_isqrt(dd);
+    for (int a = 0; a < 3; ++a) {
+        int64_t off = or_rdiv(tau_u * D[a], (int64_t)r);
+        E[a] = q[a] + off;
+        S[a] = ((int64_t)r <= tau_u) ? o[a] : q[a] - off;
+    }
+    *r_out = r;
+    return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* step 3: the set of voxels the closed segment [S, E] touches          */
+/* ------------------------------------------------------------------ */
+
+typedef struct { int64_t num, den; } frac; /* den > 0 */
+
+static int frac_cmp(const void *pa, const void *pb)
+{
+    const frac *a = (const frac *)pa, *b = (const frac *)pb;
+    __int128 l = (__int128)a->num * b->den, r = (__int128)b->num * a->den;
+    return (l > r) - (l < r);
+}
+
+/* Voxel of P(t) = S + t (E - S) at rational t = num/den (den > 0), under
+ * half-open ownership [k*1024, (k+1)*1024). */
+static void voxel_at(const int64_t S[3], const int64_t L[3], __int128 num, __int128 den, int64_t g[3])
+{
+    for (int a = 0; a < 3; ++a)
+        g[a] = (int64_t)floor_div128((__int128)S[a] * den + num * L[a], den * 1024);
+}
+
+/* Writes every voxel of { floor(P(t)/1024) : t in [0,1] } to out (as xyz
+ * triples, in increasing t) and returns how many there are, or -1 if more
+ * than max. The set is evaluated by its definition: P(t)/1024 changes voxel
+ * only at times where a coordinate reaches a multiple of 1024, so the set is
+ * the voxels at t = 0, t = 1, at every such time, and at one time strictly
+ * inside each interval between consecutive such times. */
+int or_segment_voxels(const int64_t S[3], const int64_t E[3], int64_t *out, int max)
+{
+    int64_t L[3] = {E[0] - S[0], E[1] - S[1], E[2] - S[2]};
+    /* event times: all t in [0,1] where S_a + t L_a is a multiple of 1024 */
+    int cap = 8;
+    for (int a = 0; a < 3; ++a) cap += (int)((L[a] < 0 ? -L[a] : L[a]) / 1024) + 2;
+    frac *ev = (frac *)malloc(sizeof(frac) * (size_t)cap);
+    if (!ev) return -1;
+    int ne = 0;
+    ev[ne++] = (frac){0, 1};
+    ev[ne++] = (frac){1, 1};
+    for (int a = 0; a < 3; ++a) {
+        if (L[a] == 0) continue;
+        int64_t lo = S[a] < E[a] ? S[a] : E[a];
+        int64_t hi = S[a] < E[a] ? E[a] : S[a];
+        int64_t k0 = floor_div(lo + 1023, 1024); /* smallest multiple >= lo */
+        for (int64_t k = k0; k * 1024 <= hi; ++k) {
+            int64_t num = k * 1024 - S[a];
+            int64_t den = L[a];
+            if (den < 0) { num = -num; den = -den; }
+            ev[ne++] = (frac){num, den};
+        }
+    }
+    qsort(ev, (size_t)ne, sizeof(frac), frac_cmp);
+
+    int n = 0;
+    int64_t g[3], prev[3] = {0, 0, 0};
+    int have = 0;
+    for (int i = 0; i < ne; ++i) {
+        /* the event time itself */
+        for (int pass = 0; pass < 2; ++pass) {
+            __int128 num, den;
+            if (pass == 0) {
+                num = ev[i].num;
+                den = ev[i].den;
+            } else {
+                if (i + 1 >= ne) break;
+                if (frac_cmp(&ev[i], &ev[i + 1]) == 0) continue;
+                /* midpoint of (ev[i], ev[i+1]) */
+                num = (__int128)ev[i].num * ev[i + 1].den + (__int128)ev[i + 1].num * ev[i].den;
+                den = (__int128)2 * ev[i].den * ev[i + 1].den;
+            }
+            voxel_at(S, L, num, den, g);
+            if (have && g[0] == prev[0] && g[1] == prev[1] && g[2] == prev[2]) continue;
+            if (n >= max) { free(ev); return -1; }
+            out[3 * n + 0] = g[0];
+            out[3 * n + 1] = g[1];
+            out[3 * n + 2] = g[2];
+            prev[0] = g[0]; prev[1] = g[1]; prev[2] = g[2];
+            have = 1;
+            ++n;
+        }
+    }
+    free(ev);
+    return n;
+}
+
+/* ------------------------------------------------------------------ */
+/* step 4: the signed distance a voxel receives, and its candidate key  */
+/* ------------------------------------------------------------------ */
+
+/* s = clamp(rdiv((q - c) . D, r), -tau, +tau) with c the voxel centre in
+ * fixed point (c = 1024 g + 512): the voxel centre projected onto the ray
+ * and measured from the scan point, positive on the sensor side. */
+int64_t or_voxel_sdf(const int64_t q[3], const int64_t D[3], uint64_t r, const int64_t g[3], int64_t tau_u)
+{
+    int64_t dot = 0;
+    for (int a = 0; a < 3; ++a) dot += (q[a] - (1024 * g[a] + 512)) * D[a];
+    int64_t s = or_rdiv(dot, (int64_t)r);
+    if (s > tau_u) s = tau_u;
+    if (s < -tau_u) s = -tau_u;
+    return s;
+}
+
+/* key = |s| << 48 | i << 16 | (uint16)s. The smallest key of a voxel is the
+ * candidate with the smallest |s|, ties to the lowest point index. */
+uint64_t or_key(int64_t s, uint64_t i)
+{
+    uint64_t as = (uint64_t)(s < 0 ? -s : s);
+    return (as << 48) | ((i & 0xffffffffULL) << 16) | (uint64_t)(uint16_t)(int16_t)s;
+}
+
+/* ------------------------------------------------------------------ */
+/* map: window over the global volume G, plus the store of what left it */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t key[3];
+    int16_t *sdf, *w; /* CHUNK^3 each, [x][y][z] z fastest */
+} chunk_t;
+
+typedef struct {
+    int32_t dims[3];
+    int32_t origin[3];
+    double voxel_size, scale;
+    int64_t tau_u, w_max;
+    int64_t nvox;
+    int16_t *sdf, *w; /* resident window, slot = floor_mod(g, dims) */
+    uint64_t *K;      /* per-scan volume V as candidate keys, EMPTY = none */
+    int64_t *touched; /* slots whose key left EMPTY during the current scan */
+    int64_t ntouched;
+    /* store: open-addressing hash of chunks keyed by floor_div(g, CHUNK) */
+    chunk_t *tab;
+    int64_t tab_cap, tab_n;
+} omap;
+
+static int64_t slot_of(const omap *m, const int64_t g[3])
+{
+    int64_t sx = floor_mod(g[0], m->dims[0]);
+    int64_t sy = floor_mod(g[1], m->dims[1]);
+    int64_t sz = floor_mod(g[2], m->dims[2]);
+    return (sx * m->dims[1] + sy) * m->dims[2] + sz;
+}
+
+static int in_window(const int32_t origin[3], const int32_t dims[3], const int64_t g[3])
+{
+    for (int a = 0; a < 3; ++a)
+        if (g[a] < origin[a] || g[a] >= (int64_t)origin[a] + dims[a]) return 0;
+    return 1;
+}
+
+static uint64_t hash3(const int64_t k[3])
+{
+    uint64_t h = (uint64_t)k[0] * 0x9E3779B97F4A7C15ULL;
+    h ^= (uint64_t)k[1] * 0xC2B2AE3D27D4EB4FULL + (h << 6) + (h >> 2);
+    h ^= (uint64_t)k[2] * 0x165667B19E3779F9ULL + (h << 6) + (h >> 2);
+    return h;
+}
+
+static chunk_t *store_find(omap *m, const int64_t k[3], int create)
+{
+    if (create && (m->tab_n + 1) * 2 > m->tab_cap) {
+        int64_t ncap = m->tab_cap ? m->tab_cap * 2 : 1024;
+        chunk_t *nt = (chunk_t *)calloc((size_t)ncap, sizeof(chunk_t));
+        if (!nt) return NULL;
+        for (int64_t i = 0; i < m->tab_cap; ++i) {
+            if (!m->tab[i].sdf) continue;
+            uint64_t h = hash3(m->tab[i].key) & (uint64_t)(ncap - 1);
+            while (nt[h].sdf) h = (h + 1) & (uint64_t)(ncap - 1);
+            nt[h] = m->tab[i];
+        }
+        free(m->tab);
+        m->tab = nt;
+        m->tab_cap = ncap;
+    }
+    if (m->tab_cap == 0) return NULL;
+    uint64_t h = hash3(k) & (uint64_t)(m->tab_cap - 1);
+    while (m->tab[h].sdf) {
+        if (m->tab[h].key[0] == k[0] && m->tab[h].key[1] == k[1] && m->tab[h].key[2] == k[2]) return &m->tab[h];
+        h = (h + 1) & (uint64_t)(m->tab_cap - 1);
+    }
+    if (!create) return NULL;
+    chunk_t *c = &m->tab[h];
+    c->sdf = (int16_t *)calloc(CHUNK * CHUNK * CHUNK, sizeof(int16_t));
+    c->w = (int16_t *)calloc(CHUNK * CHUNK * CHUNK, sizeof(int16_t));
+    if (!c->sdf || !c->w) return NULL;
+    c->key[0] = k[0]; c->key[1] = k[1]; c->key[2] = k[2];
+    m->tab_n++;
+    return c;
+}
+
+static int64_t chunk_index(const int64_t g[3])
+{
+    return (floor_mod(g[0], CHUNK) * CHUNK + floor_mod(g[1], CHUNK)) * CHUNK + floor_mod(g[2], CHUNK);
+}
+
+static void chunk_key(const int64_t g[3], int64_t k[3])
+{
+    for (int a = 0; a < 3; ++a) k[a] = floor_div(g[a], CHUNK);
+}
+
+/* store[g] = (sdf, w) */
+static int store_put(omap *m, const int64_t g[3], int16_t sdf, int16_t w)
+{
+    int64_t k[3];
+    chunk_key(g, k);
+    chunk_t *c = store_find(m, k, sdf != 0 || w != 0);
+    if (!c) return (sdf == 0 && w == 0) ? OR_OK : OR_ENOMEM;
+    int64_t i = chunk_index(g);
+    c->sdf[i] = sdf;
+    c->w[i] = w;
+    return OR_OK;
+}
+
+/* (sdf, w) = store.pop(g, (0, 0)); a popped voxel reads (0, 0) afterwards */
+static void store_pop(omap *m, const int64_t g[3], int16_t *sdf, int16_t *w, int pop)
+{
+    int64_t k[3];
+    chunk_key(g, k);
+    chunk_t *c = store_find(m, k, 0);
+    if (!c) { *sdf = 0; *w = 0; return; }
+    int64_t i = chunk_index(g);
+    *sdf = c->sdf[i];
+    *w = c->w[i];
+    if (pop) { c->sdf[i] = 0; c->w[i] = 0; }
+}
+
+omap *or_map_create(const int32_t dims[3], const int32_t origin[3], double voxel_size,
+                    int32_t tau_u, int32_t w_max)
+{
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 1) return NULL;
+    if (!(voxel_size > 0) || tau_u < 1 || tau_u > 32767 || w_max < 1 || w_max > 32767) return NULL;
+    omap *m = (omap *)calloc(1, sizeof(omap));
+    if (!m) return NULL;
+    memcpy(m->dims, dims, sizeof(m->dims));
+    memcpy(m->origin, origin, sizeof(m->origin));
+    m->voxel_size = voxel_size;
+    m->scale = 1024.0 / voxel_size;
+    m->tau_u = tau_u;
+    m->w_max = w_max;
+    m->nvox = (int64_t)dims[0] * dims[1] * dims[2];
+    m->sdf = (int16_t *)calloc((size_t)m->nvox, sizeof(int16_t));
+    m->w = (int16_t *)calloc((size_t)m->nvox, sizeof(int16_t));
+    m->K = (uint64_t *)malloc((size_t)m->nvox * sizeof(uint64_t));
+    m->touched = (int64_t *)malloc((size_t)m->nvox * sizeof(int64_t));
+    if (!m->sdf || !m->w || !m->K || !m->touched) {
+        free(m->sdf); free(m->w); free(m->K); free(m->touched); free(m);
+        return NULL;
+    }
+    for (int64_t i = 0; i < m->nvox; ++i) m->K[i] = KEY_EMPTY;
+    return m;
+}
+
+void or_map_destroy(omap *m)
+{
+    if (!m) return;
+    for (int64_t i = 0; i < m->tab_cap; ++i) {
+        free(m->tab[i].sdf);
+        free(m->tab[i].w);
+    }
+    free(m->tab);
+    free(m->sdf); free(m->w); free(m->K); free(m->touched);
+    free(m);
+}
+
+/* Per-scan volume V (candidates only, no merge): for every point i with a
+ * ray, for every voxel g of its band segment inside the window,
+ * K[g] = min(K[g], key(s, i)). stats: points_valid, visits. */
+static int build_volume(omap *m, const float *xyz, int64_t n, const double M[16], int64_t *valid, int64_t *visits)
+{
+    int64_t o[3];
+    if (!or_quantise_origin(M, m->scale, o)) return OR_EINVAL;
+    int64_t cap = 4096;
+    int64_t *vox = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)cap);
+    if (!vox) return OR_ENOMEM;
+    *valid = 0;
+    *visits = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t q[3], D[3], S[3], E[3];
+        uint64_t r;
+        if (!or_quantise_point(&xyz[3 * i], M, m->scale, q)) continue;
+        if (!or_band(q, o, m->tau_u, D, &r, S, E)) continue;
+        (*valid)++;
+        int nv = or_segment_voxels(S, E, vox, (int)cap);
+        if (nv < 0) { free(vox); return OR_ENOMEM; }
+        for (int k = 0; k < nv; ++k) {
+            int64_t *g = &vox[3 * k];
+            if (!in_window(m->origin, m->dims, g)) continue;
+            (*visits)++;
+            int64_t s = or_voxel_sdf(q, D, r, g, m->tau_u);
+            uint64_t key = or_key(s, (uint64_t)i);
+            int64_t sl = slot_of(m, g);
+            if (m->K[sl] == KEY_EMPTY) m->touched[m->ntouched++] = sl;
+            if (key < m->K[sl]) m->K[sl] = key;
+        }
+    }
+    free(vox);
+    return OR_OK;
+}
+
+/* Eq. (1) and Eq. (2) with v.weight = 1 per scan:
+ *   g.value  = rdiv(g.value * g.weight + v.value, g.weight + 1)
+ *   g.weight = min(w_max, g.weight + 1)
+ * applied to every voxel that V holds a value for; V is then emptied.
+ * (Each voxel's update is independent of the others, so visiting the
+ * touched voxels in any order gives the same map.) */
+static int64_t merge_volume(omap *m)
+{
+    int64_t U = 0;
+    for (int64_t t = 0; t < m->ntouched; ++t) {
+        int64_t sl = m->touched[t];
+        uint64_t key = m->K[sl];
+        int64_t v = (int64_t)(int16_t)(uint16_t)(key & 0xffff);
+        int64_t gw = m->w[sl];
+        int64_t gv = m->sdf[sl];
+        m->sdf[sl] = (int16_t)or_rdiv(gv * gw + v, gw + 1);
+        m->w[sl] = (int16_t)(gw + 1 < m->w_max ? gw + 1 : m->w_max);
+        m->K[sl] = KEY_EMPTY;
+        ++U;
+    }
+    m->ntouched = 0;
+    return U;
+}
+
+/* stats[4] = points_in, points_valid, visits, voxels_updated */
+int or_integrate(omap *m, const float *xyz, int64_t n, const double M[16], int64_t *stats)
+{
+    if (!m || n < 0 || (n > 0 && !xyz) || !M) return OR_EINVAL;
+    if (n > 0xffffffffLL) return OR_EINVAL;
+    for (int k = 0; k < 12; ++k)
+        if (!isfinite(M[k])) return OR_EINVAL;
+    int64_t o[3];
+    if (!or_quantise_origin(M, m->scale, o)) return OR_EINVAL;
+    int64_t valid = 0, visits = 0;
+    int rc = build_volume(m, xyz, n, M, &valid, &visits);
+    if (rc != OR_OK) return rc;
+    int64_t U = merge_volume(m);
+    if (stats) {
+        stats[0] = n;
+        stats[1] = valid;
+        stats[2] = visits;
+        stats[3] = U;
+    }
+    return OR_OK;
+}
+
+/* The per-scan volume V alone, as keys over the window in slot order
+ * (EMPTY where no ray reached), without touching the map. */
+int or_volume(omap *m, const float *xyz, int64_t n, const double M[16], uint64_t *keys_out)
+{
+    if (!m || n < 0 || !M || !keys_out) return OR_EINVAL;
+    int64_t valid, visits;
+    int rc = build_volume(m, xyz, n, M, &valid, &visits);
+    if (rc != OR_OK) return rc;
+    memcpy(keys_out, m->K, (size_t)m->nvox * sizeof(uint64_t));
+    for (int64_t t = 0; t < m->ntouched; ++t) m->K[m->touched[t]] = KEY_EMPTY;
+    m->ntouched = 0;
+    return OR_OK;
+}
+
+/* Move the window to new_origin. Every voxel leaving the window is written
+ * to the store and its slot cleared; every voxel entering it is taken from
+ * the store, or (0, 0) if the store has none. Slot addressing floor_mod(g, n)
+ * means a voxel that stays never moves. */
+int or_shift(omap *m, const int32_t new_origin[3])
+{
+    if (!m || !new_origin) return OR_EINVAL;
+    for (int64_t sx = 0; sx < m->dims[0]; ++sx)
+        for (int64_t sy = 0; sy < m->dims[1]; ++sy)
+            for (int64_t sz = 0; sz < m->dims[2]; ++sz) {
+                int64_t s[3] = {sx, sy, sz};
+                int64_t g_old[3], g_new[3];
+                for (int a = 0; a < 3; ++a) {
+                    /* the unique g = s (mod n) inside [origin, origin + n) */
+                    g_old[a] = m->origin[a] + floor_mod(s[a] - m->origin[a], m->dims[a]);
+                    g_new[a] = new_origin[a] + floor_mod(s[a] - new_origin[a], m->dims[a]);
+                }
+                if (g_old[0] == g_new[0] && g_old[1] == g_new[1] && g_old[2] == g_new[2]) continue;
+                int64_t sl = (sx * m->dims[1] + sy) * m->dims[2] + sz;
+                if (store_put(m, g_old, m->sdf[sl], m->w[sl]) != OR_OK) return OR_ENOMEM;
+                store_pop(m, g_new, &m->sdf[sl], &m->w[sl], 1);
+            }
+    memcpy(m->origin, new_origin, sizeof(m->origin));
+    return OR_OK;
+}
+
+/* Global box [lo, hi) in C order [x][y][z]: resident value, else stored
+ * value, else (0, 0). */
+int or_readback(omap *m, const int32_t lo[3], const int32_t hi[3], int16_t *sdf, int16_t *w)
+{
+    if (!m || !lo || !hi || !sdf || !w) return OR_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (hi[a] < lo[a]) return OR_EINVAL;
+    int64_t ny = hi[1] - lo[1], nz = hi[2] - lo[2];
+    for (int64_t x = lo[0]; x < hi[0]; ++x)
+        for (int64_t y = lo[1]; y < hi[1]; ++y)
+            for (int64_t z = lo[2]; z < hi[2]; ++z) {
+                int64_t g[3] = {x, y, z};
+                int64_t o = ((x - lo[0]) * ny + (y - lo[1])) * nz + (z - lo[2]);
+                if (in_window(m->origin, m->dims, g)) {
+                    int64_t sl = slot_of(m, g);
+                    sdf[o] = m->sdf[sl];
+                    w[o] = m->w[sl];
+                } else {
+                    store_pop(m, g, &sdf[o], &w[o], 0);
+                }
+            }
+    return OR_OK;
+}
+
+/* The resident window in slot order (the raw device-layout view). */
+int or_window(omap *m, int16_t *sdf, int16_t *w, int32_t origin[3])
+{
+    if (!m) return OR_EINVAL;
+    if (sdf) memcpy(sdf, m->sdf, (size_t)m->nvox * sizeof(int16_t));
+    if (w) memcpy(w, m->w, (size_t)m->nvox * sizeof(int16_t));
+    if (origin) memcpy(origin, m->origin, sizeof(m->origin));
+    return OR_OK;
+}
+
+int64_t or_store_chunks(omap *m) { return m ? m->tab_n : 0; }
+
+/* Recentre rule of the local map: when the sensor voxel position o (fixed
+ * point) is farther than radius_u (fixed point) from the window centre
+ * 1024 (origin + dims/2), the window is re-centred on the chunk-grid point
+ * nearest the sensor voxel: origin' = chunk * floor((floor(o/1024) +
+ * chunk/2) / chunk) - dims/2. Returns 1 and writes origin' if a shift is
+ * due, 0 otherwise, -1 for an unrepresentable pose. With force = 1 the
+ * origin is always computed (placement of the first window). */
+int or_recentre(const int32_t dims[3], const int32_t origin[3], double voxel_size, const double M[16],
+                int64_t radius_u, int32_t chunk, int force, int32_t out[3])
+{
+    int64_t o[3];
+    if (!or_quantise_origin(M, 1024.0 / voxel_size, o)) return -1;
+    __int128 d2 = 0;
+    for (int a = 0; a < 3; ++a) {
+        __int128 c = (__int128)1024 * ((int64_t)origin[a] + dims[a] / 2);
+        __int128 d = (__int128)o[a] - c;
+        d2 += d * d;
+    }
+    if (!force && d2 <= (__int128)radius_u * radius_u) return 0;
+    for (int a = 0; a < 3; ++a) {
+        int64_t sv = floor_div(o[a], 1024);
+        out[a] = (int32_t)(chunk * floor_div(sv + chunk / 2, chunk) - dims[a] / 2);
+    }
+    return 1;
+}

@@ -1,0 +1,362 @@
+"""Pins of the CPU oracle against facts fixed outside it: exact arithmetic,
+brute force over small voxel grids, hand-derived closed forms (golden/),
+and invariants of the method. None of these reuses the oracle's own code."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import brute
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# -- rdiv / isqrt: textbook definitions --------------------------------------
+
+def test_rdiv_exhaustive_small():
+    for n in range(-300, 301):
+        for d in range(1, 40):
+            assert oracle.rdiv(n, d) == brute.round_half_away(Fraction(n, d)), (n, d)
+
+
+def test_rdiv_examples_and_large():
+    assert [oracle.rdiv(1, 3), oracle.rdiv(3, 2), oracle.rdiv(-3, 2), oracle.rdiv(2, 4), oracle.rdiv(-1, 2)] == \
+        [0, 2, -2, 1, -1]
+    g = np.random.default_rng(7)
+    for _ in range(3000):
+        n = int(g.integers(-(2 ** 52), 2 ** 52))
+        d = int(g.integers(1, 2 ** 34))
+        assert oracle.rdiv(n, d) == brute.round_half_away(Fraction(n, d))
+
+
+def test_isqrt():
+    for n in range(0, 5000):
+        assert oracle.isqrt(n) == math.isqrt(n)
+    g = np.random.default_rng(8)
+    vals = [int(v) for v in g.integers(0, 2 ** 63, size=3000, dtype=np.uint64)]
+    vals += [k * k for k in (2 ** 31, 2 ** 32 - 1, 3037000499)] + [k * k - 1 for k in (2 ** 31, 2 ** 32 - 1)]
+    vals += [2 ** 64 - 1, 3 * 2 ** 62]
+    for n in vals:
+        assert oracle.isqrt(n) == math.isqrt(n), n
+
+
+# -- transform + quantisation: exact fma emulation ---------------------------
+
+def test_quantise_identity_grid_points():
+    scale = 1024.0 / 0.05
+    for p in [(0.05, 0.1, -0.15), (1.0, -2.0, 0.5), (0.0, 0.0, 0.0)]:
+        q = oracle.quantise_point(p, np.eye(4), scale)
+        expect = [round(float(np.float32(v)) * scale) for v in p]
+        assert list(q) == expect
+
+
+def test_quantise_random_poses_match_exact_fma():
+    g = np.random.default_rng(9)
+    for k in range(400):
+        M = synth.fuzz_pose(1000 + k, max_t=20.0)
+        scale = 1024.0 / float(g.choice([0.05, 0.064, 0.08, 0.1, 1.0 / 3.0]))
+        p = g.uniform(-60, 60, size=3).astype(np.float32)
+        q = oracle.quantise_point(p, M, scale)
+        ref = brute.quantise(p, M, scale)
+        assert (q is None and ref is None) or list(q) == ref
+        o = oracle.quantise_origin(M, scale)
+        assert list(o) == [round(M[a][3] * scale) for a in range(3)]
+
+
+def test_quantise_half_even_and_range():
+    # w * scale = 2.5 exactly -> 2 (half to even); 3.5 -> 4
+    M = np.eye(4)
+    assert list(oracle.quantise_point((2.5 / 1024, 3.5 / 1024, -2.5 / 1024), M, 1024.0)) == [2, 4, -2]
+    # |q| >= 2^30 is dropped; non-finite is dropped
+    assert oracle.quantise_point((2.0 ** 20, 0, 0), M, 1024.0) is None
+    assert oracle.quantise_point((2.0 ** 20 - 1, 0, 0), M, 1024.0) is not None
+    assert oracle.quantise_point((np.nan, 0, 0), M, 1024.0) is None
+    assert oracle.quantise_point((np.inf, 0, 0), M, 1024.0) is None
+
+
+# -- band --------------------------------------------------------------------
+
+def test_band_closed_forms():
+    # axis-parallel ray: off is exactly tau along the axis
+    D, r, S, E = oracle.band([20580, 512, 512], [512, 512, 512], 3072)
+    assert list(D) == [20068, 0, 0] and r == 20068
+    assert list(S) == [17508, 512, 512] and list(E) == [23652, 512, 512]
+    # point within tau of the sensor: the band starts at the sensor
+    D, r, S, E = oracle.band([1000, 0, 0], [0, 0, 0], 3072)
+    assert list(S) == [0, 0, 0] and list(E) == [4072, 0, 0]
+    # zero-length ray: no band
+    assert oracle.band([5, 5, 5], [5, 5, 5], 3072) is None
+    # diagonal: |D|^2 = 3 * 1000^2, r = 1732, off = rdiv(3072 * 1000, 1732) = 1774 (1773.67)
+    D, r, S, E = oracle.band([11000, 11000, 11000], [10000, 10000, 10000], 3072)
+    assert r == 1732 and list(E) == [12774] * 3 and list(S) == [10000] * 3
+
+
+# -- traversal: closed forms, brute force, invariants ------------------------
+
+def test_segment_closed_forms():
+    cases = json.load(open(os.path.join(GOLDEN, "segment_closed_forms.json")))["cases"]
+    for c in cases:
+        got = oracle.segment_voxels(c["S"], c["E"]).tolist()
+        assert got == c["voxels"], c["name"]
+
+
+def _brute_box(S, E):
+    lo = [min(S[a], E[a]) // 1024 - 1 for a in range(3)]
+    hi = [max(S[a], E[a]) // 1024 + 2 for a in range(3)]
+    return lo, hi
+
+
+def _check_invariants(S, E, vox):
+    assert tuple(vox[0]) == tuple(s // 1024 for s in S)
+    assert tuple(vox[-1]) == tuple(e // 1024 for e in E)
+    for a in range(3):
+        steps = np.diff(vox[:, a])
+        assert np.all(np.abs(steps) <= 1)
+        sgn = np.sign(E[a] - S[a])
+        assert np.all(steps * sgn >= 0)
+    assert len({tuple(v) for v in vox}) == len(vox)
+
+
+@pytest.mark.parametrize("mode", ["random", "grid", "corner"])
+def test_segment_vs_brute_force(mode):
+    g = np.random.default_rng({"random": 11, "grid": 12, "corner": 13}[mode])
+    for _ in range(150):
+        if mode == "random":
+            S = [int(v) for v in g.integers(-4096, 4096, size=3)]
+            E = [int(v) for v in g.integers(-4096, 4096, size=3)]
+        elif mode == "grid":  # endpoints on voxel faces / edges / corners
+            S = [int(v) * 512 for v in g.integers(-8, 8, size=3)]
+            E = [int(v) * 512 for v in g.integers(-8, 8, size=3)]
+        else:  # segments through cell corners at shared crossing times
+            base = [int(v) * 1024 for v in g.integers(-3, 3, size=3)]
+            k = [int(v) for v in g.integers(-3, 4, size=3)]
+            S = base
+            E = [base[a] + 1024 * k[a] for a in range(3)]
+        vox = oracle.segment_voxels(S, E)
+        lo, hi = _brute_box(S, E)
+        ref = brute.segment_voxels_brute(S, E, lo, hi)
+        assert sorted(map(tuple, vox.tolist())) == sorted(ref), (S, E)
+        _check_invariants(S, E, vox)
+
+
+# -- signed distance: the single-plane closed form ---------------------------
+
+def _single_point_map(prof, tau_u, vs, j=0, k=0):
+    m = oracle.OracleMap((64, 8, 8), (0, 0, 0), vs, tau_u, 64)
+    pose = np.eye(4)
+    pose[:3, 3] = [prof["sensor_m"][0], prof["sensor_m"][1] + j, prof["sensor_m"][2] + k]
+    m.integrate(np.array([prof["point_sensor_m"]], dtype=np.float32), pose)
+    return m
+
+
+def test_plane_profile_closed_form():
+    d = json.load(open(os.path.join(GOLDEN, "plane_profile.json")))
+    for side in ("plus_x", "minus_x"):
+        prof = d[side]
+        for j, k in [(0, 0), (1, 2), (3, 3)]:
+            m = _single_point_map(prof, d["tau_u"], d["voxel_size_m"], j, k)
+            sdf, w = m.readback((0, 0, 0), (64, 8, 8))
+            xs = np.nonzero(w[:, j, k])[0].tolist()
+            assert xs == prof["voxels_x"], side
+            assert sdf[xs, j, k].tolist() == prof["sdf"], side
+            assert int(w.sum()) == len(xs)  # nothing else touched
+            m.close()
+
+
+# -- min rule: brute force over an 8^3 window --------------------------------
+
+def _tiny_scan(seed, n):
+    g = np.random.default_rng(seed)
+    pts = g.uniform(-2.0, 2.0, size=(n, 3))
+    # repeat some points so that exact ties in |s| occur across indices
+    pts[n // 2:n // 2 + 3] = pts[0]
+    pts[-1] = np.nan
+    return pts.astype(np.float32)
+
+
+@pytest.mark.parametrize("seed", [21, 22, 23])
+def test_volume_vs_brute_force(seed):
+    vs, tau = 0.5, 1536
+    scale = 1024.0 / vs
+    dims, origin = (8, 8, 8), (-4, -4, -4)
+    xyz = _tiny_scan(seed, 24)
+    M = synth.fuzz_pose(seed, max_t=0.8)
+    m = oracle.OracleMap(dims, origin, vs, tau, 64)
+    keys = m.volume(xyz, M)  # slot order; origin multiple of dims -> slot = g mod 8
+    best = brute.volume_brute(xyz, M, scale, tau, origin, dims)
+    seen = 0
+    for gx in range(origin[0], origin[0] + 8):
+        for gy in range(origin[1], origin[1] + 8):
+            for gz in range(origin[2], origin[2] + 8):
+                kk = int(keys[gx % 8, gy % 8, gz % 8])
+                if (gx, gy, gz) in best:
+                    a, i, s = best[(gx, gy, gz)]
+                    assert kk == (a << 48) | (i << 16) | (s & 0xFFFF)
+                    seen += 1
+                else:
+                    assert kk == 0xFFFFFFFFFFFFFFFF
+    assert seen > 50
+    m.close()
+
+
+# -- merge: Eq. (1) / Eq. (2) closed forms and invariants --------------------
+
+def _profile_run(values_scans, w_max=64):
+    """Integrate axis-parallel single-ray scans whose plane distance varies,
+    returning the resulting (sdf, w) profile along x."""
+    m = oracle.OracleMap((64, 4, 4), (0, 0, 0), 1.0, 3072, w_max)
+    for X in values_scans:
+        pose = np.eye(4)
+        pose[:3, 3] = [0.5, 0.5, 0.5]
+        m.integrate(np.array([[X - 0.5, 0.0, 0.0]], dtype=np.float32), pose)
+    sdf, w = m.readback((0, 0, 0), (64, 1, 1))
+    m.close()
+    return sdf[:, 0, 0].astype(int), w[:, 0, 0].astype(int)
+
+
+def test_merge_identical_scans_keep_value():
+    X = 20580 / 1024
+    base_sdf, base_w = _profile_run([X])
+    for k in (2, 5, 70):
+        sdf, w = _profile_run([X] * k)
+        assert np.array_equal(sdf, base_sdf)
+        assert np.array_equal(w, np.where(base_w > 0, min(k, 64), 0))
+
+
+def test_merge_two_scans_average():
+    Xa, Xb = 20580 / 1024, 20000 / 1024
+    a_sdf, a_w = _profile_run([Xa])
+    b_sdf, b_w = _profile_run([Xb])
+    ab_sdf, ab_w = _profile_run([Xa, Xb])
+    for x in range(64):
+        if a_w[x] and b_w[x]:
+            assert ab_sdf[x] == brute.round_half_away(Fraction(int(a_sdf[x]) + int(b_sdf[x]), 2))
+            assert ab_w[x] == 2
+        elif a_w[x] or b_w[x]:
+            assert ab_sdf[x] == (a_sdf[x] if a_w[x] else b_sdf[x]) and ab_w[x] == 1
+
+
+def test_merge_at_weight_cap():
+    Xa, Xb = 20580 / 1024, 20100 / 1024
+    cap = 5
+    sdf_a, w_a = _profile_run([Xa] * 7, w_max=cap)
+    sdf_b, w_b = _profile_run([Xb])
+    sdf, w = _profile_run([Xa] * 7 + [Xb], w_max=cap)
+    both = 0
+    for x in range(64):
+        if w_a[x] and w_b[x]:
+            both += 1
+            assert w[x] == cap
+            assert sdf[x] == brute.round_half_away(Fraction(cap * int(sdf_a[x]) + int(sdf_b[x]), cap + 1))
+    assert both >= 5
+
+
+def test_merge_invariants_on_room_scans():
+    w1 = synth.config1()
+    spec = w1.maps[0]
+    m = oracle.OracleMap.from_spec(spec)
+    prev_w = np.zeros(spec.dims, np.int16)
+    for k in range(4):
+        pose = synth.fuzz_pose(500 + k, max_t=0.3)
+        pose[:3, :3] = np.eye(3) if k == 0 else pose[:3, :3]
+        st = m.integrate(w1.scans[0].xyz, pose)
+        sdf, w, _ = m.window()
+        assert np.all(np.abs(sdf.astype(int)) <= spec.tau_u)
+        assert np.all((w >= 0) & (w <= spec.w_max))
+        assert np.all(w >= prev_w)
+        assert int((w != prev_w).sum()) <= st["voxels_updated"]
+        # voxels whose weight did not change kept their value bit-exactly
+        prev_w = w.copy()
+    m.close()
+
+
+def test_untouched_voxels_unchanged():
+    w1 = synth.config1()
+    spec = w1.maps[0]
+    m = oracle.OracleMap.from_spec(spec)
+    m.integrate(w1.scans[0].xyz, w1.scans[0].pose)
+    sdf0, w0, _ = m.window()
+    keys = m.volume(w1.scans[0].xyz[:4000], synth.fuzz_pose(3, 0.2))
+    st = m.integrate(w1.scans[0].xyz[:4000], synth.fuzz_pose(3, 0.2))
+    sdf1, w1_, _ = m.window()
+    untouched = keys == np.uint64(0xFFFFFFFFFFFFFFFF)
+    assert np.array_equal(sdf0[untouched], sdf1[untouched]) and np.array_equal(w0[untouched], w1_[untouched])
+    assert int((~untouched).sum()) == st["voxels_updated"]
+    m.close()
+
+
+# -- shift: readback is invariant, shift then inverse is the identity -------
+
+def test_shift_inverse_and_readback_invariance():
+    w1 = synth.config1()
+    m = oracle.OracleMap((64, 64, 64), (-32, -32, -32), 0.05, 3072, 64)
+    for k in range(3):
+        m.integrate(w1.scans[0].xyz, synth.fuzz_pose(40 + k, 0.2))
+    box_lo, box_hi = (-100, -100, -100), (100, 100, 100)
+    before = m.readback(box_lo, box_hi)
+    sdf0, w0, o0 = m.window()
+    for d in [(64, 0, 0), (-64, 64, 0), (5, -7, 3), (0, 0, -200)]:
+        new = tuple(o0[a] + d[a] for a in range(3))
+        m.shift(new)
+        after = m.readback(box_lo, box_hi)
+        assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+        m.shift(o0)
+        sdf1, w1_, o1 = m.window()
+        assert o1 == o0 and np.array_equal(sdf0, sdf1) and np.array_equal(w0, w1_)
+    m.close()
+
+
+def test_ring_run_equals_fixed_run_inside_overlap():
+    """Scans whose bands stay inside every window the ring visits give the
+    same global map as a fixed window holding all of them."""
+    xyz = synth.fuzz_scan(77, 3000, extent_m=1.0, nan_frac=0.0)
+    xyz = xyz[np.linalg.norm(xyz, axis=1) < 1.0]
+    ring = oracle.OracleMap((64, 64, 64), (-32, -32, -32), 0.05, 3072, 64)
+    fixed = oracle.OracleMap((128, 128, 128), (-64, -64, -64), 0.05, 3072, 64)
+    origins = [(-32, -32, -32), (-28, -32, -32), (-32, -36, -30), (-34, -30, -32)]
+    for k, o in enumerate(origins):
+        ring.shift(o)
+        pose = np.eye(4)
+        pose[:3, 3] = [0.01 * k, -0.02 * k, 0.0]
+        ring.integrate(xyz, pose)
+        fixed.integrate(xyz, pose)
+    a = ring.readback((-64, -64, -64), (64, 64, 64))
+    b = fixed.readback((-64, -64, -64), (64, 64, 64))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert int((a[1] > 0).sum()) > 1000
+    ring.close()
+    fixed.close()
+
+
+def test_recentre_rule_closed_form():
+    dims = (512, 512, 128)
+    vs = 0.05
+    # sensor at voxel (100, -3, 0): nearest chunk-grid point is (128, 0, 0)
+    pose = np.eye(4)
+    pose[:3, 3] = [100 * vs + 0.01, -3 * vs + 0.01, 0.01]
+    due, o = oracle.recentre(dims, (0, 0, 0), vs, pose, 65536, force=True)
+    assert due and o == (128 - 256, 0 - 256, 0 - 64)
+    # at the centre: no shift; just beyond 64 voxels: shift
+    pose[:3, 3] = [0.0, 0.0, 0.0]
+    assert oracle.recentre(dims, (-256, -256, -64), vs, pose, 65536)[0] is False
+    pose[:3, 3] = [64 * vs, 0.0, 0.0]      # exactly 65536 away: not beyond
+    assert oracle.recentre(dims, (-256, -256, -64), vs, pose, 65536)[0] is False
+    pose[:3, 3] = [64 * vs + 0.001, 0.0, 0.0]
+    due, o = oracle.recentre(dims, (-256, -256, -64), vs, pose, 65536)
+    assert due and o == (64 - 256, -256, -64)
+
+
+def test_stats_counts():
+    m = oracle.OracleMap((64, 8, 8), (0, 0, 0), 1.0, 3072, 64)
+    pose = np.eye(4)
+    pose[:3, 3] = [0.5, 0.5, 0.5]
+    pts = np.array([[19.59765625, 0, 0], [np.nan, 0, 0], [0.0, 0.0, 0.0], [19.59765625, 0, 0]], np.float32)
+    st = m.integrate(pts, pose)
+    # point 2 coincides with the sensor (D = 0): skipped; point 3 repeats point 0
+    assert st == dict(points_in=4, points_valid=2, visits=14, voxels_updated=7)
+    m.close()
