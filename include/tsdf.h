@@ -1,0 +1,149 @@
+/*
+ * tsdf.h -- C ABI of the MI355X TSDF-mapping library (FeatSense TSDF path,
+ * Gaal et al., arXiv 2310.05766, Sec. VI "TSDF Map Generation").
+ *
+ * The library integrates registered LiDAR scans, each taken at a given pose,
+ * into a truncated signed distance field (Sec. VI), keeps a local map that
+ * shifts after a movement threshold while writing what leaves it out and
+ * loading what re-enters it (Sec. I), and keeps the global map (Sec. VII-C).
+ *
+ * Conventions shared by every call:
+ *  - Fixed point. Positions are rounded to 1/1024 of a voxel in the global
+ *    frame; signed distances are stored in the same unit.
+ *  - Voxel storage (Sec. VI: a 16-bit value and a 16-bit weight per voxel).
+ *    Two int16 arrays (SDF, weight), each [nx][ny][nz], z fastest, indexed
+ *    by slot = floor_mod(g, dims) of the global voxel g (a ring buffer: a
+ *    voxel that stays in the window never moves when the window shifts).
+ *  - Streams. Every call on one map is ordered on that map's HIP stream.
+ *  - Errors. Every call returns a tsdf_status; no exception crosses the ABI.
+ *    TSDF_EINVAL leaves the map untouched. TSDF_EDEVICE poisons the map:
+ *    afterwards only tsdf_map_destroy is accepted.
+ *  - Threads. A map is used by one host thread at a time (TSDF_EBUSY if
+ *    not); different maps may be used concurrently.
+ */
+#ifndef TSDF_H
+#define TSDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tsdf_map tsdf_map; /* opaque: device arrays, scratch, host chunk store */
+
+typedef enum {
+    TSDF_OK = 0,
+    TSDF_EINVAL = -1,  /* bad argument; nothing was changed */
+    TSDF_ENOMEM = -2,  /* device or host allocation failed */
+    TSDF_EDEVICE = -3, /* a HIP call failed; the map is poisoned */
+    TSDF_ERANGE = -4,  /* a size exceeds what the library supports */
+    TSDF_EBUSY = -5    /* the map is in use by another host thread */
+} tsdf_status;
+
+typedef enum { TSDF_PTR_HOST = 0, TSDF_PTR_DEVICE = 1 } tsdf_ptr_kind;
+
+typedef struct {
+    int32_t dims[3];     /* window size in voxels, each >= 1; nx*ny*nz < 2^31 */
+    int32_t origin[3];   /* global voxel index of the window's min corner */
+    double voxel_size_m; /* > 0 */
+    int32_t tau_q10;     /* truncation tau in 1/1024-voxel units, 1..32767 */
+    int32_t w_max;       /* weight cap of Eq. (2), 1..32767 */
+} tsdf_map_desc;
+
+typedef struct {
+    int64_t points_in;      /* points passed in */
+    int64_t points_valid;   /* finite, representable and not at the sensor */
+    int64_t visits;         /* (ray, resident voxel) candidates */
+    int64_t voxels_updated; /* voxels that received Eq. (1)/(2) this scan */
+} tsdf_scan_stats;
+
+/* Device scratch (bytes) a map with this descriptor uses for integration. */
+size_t tsdf_scratch_bytes(const tsdf_map_desc *d);
+
+/* Create a map whose SDF and weight arrays start at (0, 0) everywhere (w = 0
+ * means unknown). hip_stream is a hipStream_t (NULL: the library creates its
+ * own stream). The library owns every allocation. */
+tsdf_status tsdf_map_create(const tsdf_map_desc *d, void *hip_stream, tsdf_map **out);
+
+/* As tsdf_map_create, on caller-owned device memory: sdf_dev and w_dev hold
+ * nx*ny*nz int16 each (layout above; the caller initialises them), and
+ * scratch_dev holds at least tsdf_scratch_bytes(d) bytes. They must outlive
+ * the map; the library never frees them. */
+tsdf_status tsdf_map_create_in(const tsdf_map_desc *d, void *sdf_dev, void *w_dev, void *scratch_dev,
+                               size_t scratch_bytes, void *hip_stream, tsdf_map **out);
+
+/* Waits for the map's stream and frees what the library owns. */
+tsdf_status tsdf_map_destroy(tsdf_map *m);
+
+/* Integrate one registered scan (Sec. VI: the min-tsdf step, then the
+ * averaging step of Eq. (1) and Eq. (2) with one unit of weight per scan).
+ *  xyz:   n_points x 3 float32, sensor frame, metres; a point with a
+ *         non-finite coordinate is no return. Point i is row i (for an
+ *         organised scan i = ring * columns + column); n_points < 2^32.
+ *  kind:  TSDF_PTR_HOST -> copied into pinned staging before the call
+ *         returns (the caller may reuse xyz at once); TSDF_PTR_DEVICE -> read
+ *         on the map's stream (must stay valid until the stream passes it).
+ *  world_T_sensor: row-major 4x4 float64 (host); only rows 0..2 are used and
+ *         they must be finite, with the sensor position representable.
+ *  stats: NULL -> the call returns without waiting for the GPU; otherwise
+ *         the call waits and fills the counts of this scan. */
+tsdf_status tsdf_integrate_scan(tsdf_map *m, const float *xyz, int64_t n_points, tsdf_ptr_kind kind,
+                                const double world_T_sensor[16], tsdf_scan_stats *stats);
+
+/* Move the window's min corner to new_origin (Sec. I: the local map is
+ * shifted; what leaves it is written out, what re-enters it is loaded).
+ * Leaving voxels go to the host chunk store (64^3-voxel chunks); entering
+ * voxels come from it, or start at (0, 0). Synchronous. */
+tsdf_status tsdf_shift(tsdf_map *m, const int32_t new_origin[3]);
+
+/* Copy the global voxel box [lo, hi) to host arrays of (hi-lo) int16 each,
+ * C order [x][y][z], z fastest: the resident value, else the stored value,
+ * else (0, 0). Synchronous. */
+tsdf_status tsdf_readback(tsdf_map *m, const int32_t lo[3], const int32_t hi[3], int16_t *sdf_out,
+                          int16_t *w_out);
+
+/* Batched form: scans that share a map are applied in array order, and the
+ * result is bit-identical to calling tsdf_integrate_scan in that order. */
+typedef struct {
+    tsdf_map *map;
+    const float *xyz;
+    int64_t n_points;
+    double pose[16];
+} tsdf_scan_desc;
+
+tsdf_status tsdf_integrate_batch(const tsdf_scan_desc *scans, int32_t count, tsdf_ptr_kind kind,
+                                 void *hip_stream, tsdf_scan_stats *stats /* count entries, nullable */);
+
+/* --- inspection and helpers (no method arithmetic beyond what is named) --- */
+
+const char *tsdf_status_string(tsdf_status s);
+
+/* Current window origin. */
+tsdf_status tsdf_map_origin(const tsdf_map *m, int32_t origin[3]);
+
+/* Device addresses of the SDF and weight arrays (layout above) and the
+ * map's stream, for callers that wrap them (e.g. as tensors). */
+tsdf_status tsdf_map_device_arrays(const tsdf_map *m, void **sdf_dev, void **w_dev, void **hip_stream);
+
+/* Local-map recentre rule (the movement threshold of Sec. I): with o the
+ * sensor position of world_T_sensor in fixed point, a shift is due when
+ * |o - 1024 (origin + dims/2)|^2 > radius_q10^2; the new origin is the
+ * chunk-grid point nearest the sensor voxel minus dims/2. force = 1 always
+ * computes it (placement of the first window). *due is 1 when a shift is
+ * due. Pure host arithmetic; the map is not changed. */
+tsdf_status tsdf_recentre_origin(const tsdf_map *m, const double world_T_sensor[16], int64_t radius_q10,
+                                 int32_t chunk, int32_t force, int32_t new_origin[3], int32_t *due);
+
+/* Number of chunks and host bytes held by the map's chunk store. */
+tsdf_status tsdf_store_info(const tsdf_map *m, int64_t *chunks, int64_t *bytes);
+
+/* Wait until the map's stream has finished all queued work. */
+tsdf_status tsdf_map_synchronize(tsdf_map *m);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSDF_H */

@@ -267,7 +267,7 @@ typedef struct {
     int16_t *sdf, *w; /* CHUNK^3 each, [x][y][z] z fastest */
 } chunk_t;
 
-typedef struct {
+typedef struct omap_s {
     int32_t dims[3];
     int32_t origin[3];
     double voxel_size, scale;
@@ -280,7 +280,10 @@ typedef struct {
     /* store: open-addressing hash of chunks keyed by floor_div(g, CHUNK) */
     chunk_t *tab;
     int64_t tab_cap, tab_n;
+    int64_t last_hit; /* index of the last chunk found, or -1 */
 } omap;
+
+static chunk_t *store_find_slow(struct omap_s *m, const int64_t k[3], int create);
 
 static int64_t slot_of(const omap *m, const int64_t g[3])
 {
@@ -306,6 +309,17 @@ static uint64_t hash3(const int64_t k[3])
 }
 
 static chunk_t *store_find(omap *m, const int64_t k[3], int create)
+{
+    if (m->last_hit >= 0) {
+        chunk_t *c = &m->tab[m->last_hit];
+        if (c->key[0] == k[0] && c->key[1] == k[1] && c->key[2] == k[2]) return c;
+    }
+    chunk_t *c = store_find_slow(m, k, create);
+    m->last_hit = c ? (int64_t)(c - m->tab) : -1;
+    return c;
+}
+
+static chunk_t *store_find_slow(omap *m, const int64_t k[3], int create)
 {
     if (create && (m->tab_n + 1) * 2 > m->tab_cap) {
         int64_t ncap = m->tab_cap ? m->tab_cap * 2 : 1024;
@@ -388,6 +402,7 @@ omap *or_map_create(const int32_t dims[3], const int32_t origin[3], double voxel
     m->tau_u = tau_u;
     m->w_max = w_max;
     m->nvox = (int64_t)dims[0] * dims[1] * dims[2];
+    m->last_hit = -1;
     m->sdf = (int16_t *)calloc((size_t)m->nvox, sizeof(int16_t));
     m->w = (int16_t *)calloc((size_t)m->nvox, sizeof(int16_t));
     m->K = (uint64_t *)malloc((size_t)m->nvox * sizeof(uint64_t));
@@ -514,9 +529,27 @@ int or_volume(omap *m, const float *xyz, int64_t n, const double M[16], uint64_t
 int or_shift(omap *m, const int32_t new_origin[3])
 {
     if (!m || !new_origin) return OR_EINVAL;
-    for (int64_t sx = 0; sx < m->dims[0]; ++sx)
-        for (int64_t sy = 0; sy < m->dims[1]; ++sy)
-            for (int64_t sz = 0; sz < m->dims[2]; ++sz) {
+    /* changed[a][s]: the voxel held by slot coordinate s on axis a differs
+     * between the two windows. A slot whose three coordinates are all
+     * unchanged holds the same voxel before and after, so it is skipped. */
+    uint8_t *changed[3];
+    int64_t *zlist = (int64_t *)malloc(sizeof(int64_t) * (size_t)m->dims[2]);
+    int64_t nz_changed = 0;
+    for (int a = 0; a < 3; ++a) {
+        changed[a] = (uint8_t *)malloc((size_t)m->dims[a]);
+        for (int64_t v = 0; v < m->dims[a]; ++v)
+            changed[a][v] = (m->origin[a] + floor_mod(v - m->origin[a], m->dims[a])) !=
+                            (new_origin[a] + floor_mod(v - new_origin[a], m->dims[a]));
+    }
+    for (int64_t v = 0; v < m->dims[2]; ++v)
+        if (changed[2][v]) zlist[nz_changed++] = v;
+    int rc = OR_OK;
+    for (int64_t sx = 0; sx < m->dims[0] && rc == OR_OK; ++sx)
+        for (int64_t sy = 0; sy < m->dims[1] && rc == OR_OK; ++sy) {
+            const int all_z = changed[0][sx] || changed[1][sy];
+            const int64_t count = all_z ? m->dims[2] : nz_changed;
+            for (int64_t iz = 0; iz < count; ++iz) {
+                const int64_t sz = all_z ? iz : zlist[iz];
                 int64_t s[3] = {sx, sy, sz};
                 int64_t g_old[3], g_new[3];
                 for (int a = 0; a < 3; ++a) {
@@ -526,9 +559,13 @@ int or_shift(omap *m, const int32_t new_origin[3])
                 }
                 if (g_old[0] == g_new[0] && g_old[1] == g_new[1] && g_old[2] == g_new[2]) continue;
                 int64_t sl = (sx * m->dims[1] + sy) * m->dims[2] + sz;
-                if (store_put(m, g_old, m->sdf[sl], m->w[sl]) != OR_OK) return OR_ENOMEM;
+                if (store_put(m, g_old, m->sdf[sl], m->w[sl]) != OR_OK) { rc = OR_ENOMEM; break; }
                 store_pop(m, g_new, &m->sdf[sl], &m->w[sl], 1);
             }
+        }
+    for (int a = 0; a < 3; ++a) free(changed[a]);
+    free(zlist);
+    if (rc != OR_OK) return rc;
     memcpy(m->origin, new_origin, sizeof(m->origin));
     return OR_OK;
 }

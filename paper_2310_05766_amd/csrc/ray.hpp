@@ -1,0 +1,222 @@
+// Per-ray device arithmetic of the TSDF path (FeatSense, arXiv 2310.05766,
+// Sec. VI): world transform and fixed-point rounding of a scan point, the
+// truncation band around it, the exact voxel walk across the band, and the
+// signed distance each walked voxel receives.
+//
+// Every integer the walk and the distance need stays below 2^53 in
+// magnitude, so it is carried in float64 registers, where adds, multiplies
+// and compares of such integers are exact and run at full rate on CDNA
+// (a 64-bit integer add costs two VALU ops, a float64 add one).
+//   |q|, |o| < 2^30          fixed-point positions
+//   |D| < 2^31               ray vector q - o
+//   |L_a| <= 3 tau + 2 < 2^17 band segment extent per axis
+//   Lambda = prod |L_a| < 2^51, crossing times scaled by Lambda < 2^52
+//   |(q - c) . D| < 2^51     distance numerator
+// Only |D|^2 (up to 3 * 2^62) needs 64-bit integers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tsdf {
+
+constexpr uint64_t kEmptyKey = ~0ull;
+constexpr double kQLimit = 1073741824.0;  // 2^30
+
+// Scan-invariant parameters, passed by value to the kernels.
+struct ScanParams {
+    double M[12];        // rows 0..2 of world_T_sensor, row-major
+    double scale;        // 1024 / voxel_size
+    int32_t o[3];        // sensor position, fixed point
+    int32_t tau;         // truncation, fixed point
+    int32_t dims[3];     // window size
+    int32_t origin[3];   // window min corner (global voxel)
+    int32_t ring0[3];    // floor_mod(origin, dims): slot of the min corner
+    int32_t pad;
+    const float *xyz;    // n x 3 float32, sensor frame
+    int64_t n;
+};
+
+// q = round-half-even(fma-chain(M, p) * scale); false for a non-finite point
+// or |q_a| >= 2^30. The chain is fixed: fma(M0, x, fma(M1, y, fma(M2, z, M3))).
+__device__ __forceinline__ bool quantise(float px, float py, float pz, const ScanParams &P, int32_t q[3])
+{
+    if (!isfinite(px) || !isfinite(py) || !isfinite(pz)) return false;
+    const double x = px, y = py, z = pz;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double w = __fma_rn(P.M[4 * a + 0], x, __fma_rn(P.M[4 * a + 1], y, __fma_rn(P.M[4 * a + 2], z, P.M[4 * a + 3])));
+        double r = rint(__dmul_rn(w, P.scale));
+        if (!(fabs(r) < kQLimit)) return false;
+        q[a] = (int32_t)r;
+    }
+    return true;
+}
+
+// floor(sqrt(n)) for n < 2^64 - 2^33: float64 estimate, then exact integer
+// correction (the estimate is within one of the answer).
+__device__ __forceinline__ uint64_t isqrt_u64(uint64_t n)
+{
+    uint64_t r = (uint64_t)sqrt((double)n);
+    while (r * r > n) --r;
+    while ((r + 1) * (r + 1) <= n) ++r;
+    return r;
+}
+
+// floor(a / d) for exact integers 0 <= a < 2^53, 0 < d < 2^34, given
+// inv_d = 1/d rounded; the estimate a * inv_d is off by less than 2^-36
+// relative to the quotient bound used, so one correction step is exact.
+// The quotient is first capped at cap (callers clamp it anyway).
+__device__ __forceinline__ double floor_div_exact(double a, double d, double inv_d, double cap)
+{
+    double k = floor(a * inv_d);
+    k = fmin(k, cap);
+    if (__fma_rn(k, d, d) <= a) k += 1.0;     // (k + 1) d <= a
+    else if (k * d > a) k -= 1.0;
+    return k;
+}
+
+// Rounded division to nearest, ties away from zero: sign(n) floor((2|n| + d) / 2d).
+__device__ __forceinline__ double rdiv_exact(double n, double d2, double inv_d2, double d, double cap)
+{
+    double a = fabs(n);
+    double k = floor_div_exact(2.0 * a + d, d2, inv_d2, cap);
+    return n < 0 ? -k : k;
+}
+
+// One ray: the scan point, its band [S, E] along the ray, and what the
+// distance of each walked voxel needs.
+struct Ray {
+    int32_t q[3];
+    double D[3];
+    double r, r2, inv_r2;  // r = isqrt(|D|^2), r2 = 2r, inv_r2 = 1/(2r)
+    int32_t S[3], E[3];
+};
+
+// D = q - o, r = isqrt(|D|^2); off = rdiv(tau D, r); E = q + off;
+// S = q - off, or S = o when r <= tau. false for D = 0.
+__device__ __forceinline__ bool make_ray(const int32_t q[3], const ScanParams &P, Ray &R)
+{
+    int64_t Di[3];
+    uint64_t dd = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Di[a] = (int64_t)q[a] - P.o[a];
+        dd += (uint64_t)(Di[a] * Di[a]);
+        R.q[a] = q[a];
+        R.D[a] = (double)Di[a];
+    }
+    if (dd == 0) return false;
+    const uint64_t r = isqrt_u64(dd);
+    R.r = (double)r;
+    R.r2 = 2.0 * R.r;
+    R.inv_r2 = 1.0 / R.r2;
+    const double tau = (double)P.tau;
+    const bool near = (double)r <= tau;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double off = rdiv_exact(tau * R.D[a], R.r2, R.inv_r2, R.r, 4.0 * tau + 4.0);
+        int32_t oi = (int32_t)off;
+        R.E[a] = q[a] + oi;
+        R.S[a] = near ? P.o[a] : q[a] - oi;
+    }
+    return true;
+}
+
+// Signed distance of the voxel whose centre gives numerator n = (q - c) . D:
+// clamp(rdiv(n, r), -tau, tau).
+__device__ __forceinline__ int32_t voxel_sdf(double n, const Ray &R, int32_t tau)
+{
+    double k = floor_div_exact(2.0 * fabs(n) + R.r, R.r2, R.inv_r2, (double)tau + 1.0);
+    int32_t s = (int32_t)fmin(k, (double)tau);
+    return n < 0 ? -s : s;
+}
+
+// key = |s| << 48 | i << 16 | (uint16)s: the smallest key of a voxel is its
+// candidate with the smallest |s|, ties to the lowest point index.
+__device__ __forceinline__ uint64_t pack_key(int32_t s, uint32_t i)
+{
+    uint32_t as = (uint32_t)(s < 0 ? -s : s);
+    return ((uint64_t)as << 48) | ((uint64_t)i << 16) | (uint64_t)(uint16_t)(int16_t)s;
+}
+
+__device__ __forceinline__ int32_t floor_div1024(int32_t v) { return v >> 10; }  // arithmetic shift
+
+// Exact walk over { floor(P(t) / 1024) : t in [0, 1] }, P(t) = S + t (E - S).
+// Axis crossings are ordered by their time t = dist / |L_a|, compared after
+// scaling every time by Lambda = product of the non-zero |L_a| (integers,
+// exact in float64). At equal times, crossings on increasing axes (which
+// take effect at t: a point on a face belongs to the upper cell) come
+// before crossings on decreasing axes (which take effect just after t).
+// Increasing crossings are taken for t <= 1, decreasing ones for t < 1.
+struct Walk {
+    int32_t g[3];
+    int32_t step[3];
+    double T[3], dT[3];
+    double lam;
+    double n;       // (q - c(g)) . D for the current voxel
+    double dn[3];   // change of n per +1 step on each axis: -1024 D_a
+};
+
+__device__ __forceinline__ void walk_init(const Ray &R, Walk &W)
+{
+    double L[3], absL[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        L[a] = (double)(R.E[a] - R.S[a]);
+        absL[a] = fabs(L[a]);
+        W.g[a] = floor_div1024(R.S[a]);
+        W.step[a] = L[a] > 0 ? 1 : (L[a] < 0 ? -1 : 0);
+    }
+    const double f0 = absL[0] > 0 ? absL[0] : 1.0;
+    const double f1 = absL[1] > 0 ? absL[1] : 1.0;
+    const double f2 = absL[2] > 0 ? absL[2] : 1.0;
+    W.lam = f0 * f1 * f2;
+    const double other[3] = {f1 * f2, f0 * f2, f0 * f1};
+    double n = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double lo = 1024.0 * (double)W.g[a];
+        if (W.step[a] > 0) {
+            W.T[a] = (lo + 1024.0 - (double)R.S[a]) * other[a];
+        } else if (W.step[a] < 0) {
+            W.T[a] = ((double)R.S[a] - lo) * other[a];
+        } else {
+            W.T[a] = INFINITY;
+        }
+        W.dT[a] = 1024.0 * other[a];
+        n += ((double)R.q[a] - (lo + 512.0)) * R.D[a];
+        W.dn[a] = -1024.0 * R.D[a];
+    }
+    W.n = n;
+}
+
+// Advance to the next voxel; false when the segment ends.
+__device__ __forceinline__ bool walk_next(Walk &W)
+{
+    const double tm = fmin(W.T[0], fmin(W.T[1], W.T[2]));
+    const bool e0 = W.T[0] == tm, e1 = W.T[1] == tm, e2 = W.T[2] == tm;
+    const bool any_up = (e0 && W.step[0] > 0) || (e1 && W.step[1] > 0) || (e2 && W.step[2] > 0);
+    const int dir = any_up ? 1 : -1;
+    if (any_up ? (tm > W.lam) : (tm >= W.lam)) return false;
+    if (e0 && W.step[0] == dir) { W.g[0] += dir; W.T[0] += W.dT[0]; W.n += dir * W.dn[0]; }
+    if (e1 && W.step[1] == dir) { W.g[1] += dir; W.T[1] += W.dT[1]; W.n += dir * W.dn[1]; }
+    if (e2 && W.step[2] == dir) { W.g[2] += dir; W.T[2] += W.dT[2]; W.n += dir * W.dn[2]; }
+    return true;
+}
+
+// Slot of global voxel g if it lies in the window, else -1.
+__device__ __forceinline__ int64_t window_slot(const int32_t g[3], const ScanParams &P)
+{
+    int32_t s[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int32_t rel = g[a] - P.origin[a];
+        if ((uint32_t)rel >= (uint32_t)P.dims[a]) return -1;
+        int32_t v = rel + P.ring0[a];
+        s[a] = v >= P.dims[a] ? v - P.dims[a] : v;
+    }
+    return ((int64_t)s[0] * P.dims[1] + s[1]) * P.dims[2] + s[2];
+}
+
+}  // namespace tsdf

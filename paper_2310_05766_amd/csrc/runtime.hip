@@ -1,0 +1,709 @@
+// C ABI of the TSDF library: map objects, argument checks, point staging,
+// the host chunk store behind the local-map shift, readback.
+// (FeatSense, arXiv 2310.05766, Sec. VI for integration, Sec. I for the
+// shifted local map and the store of what leaves it.)
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "internal.hpp"
+
+using namespace tsdf;
+
+struct tsdf_map {
+    tsdf_map_desc d;
+    int64_t nvox = 0;
+    double scale = 0.0;
+    int16_t *sdf = nullptr, *w = nullptr;
+    bool own_arrays = false;
+    void *scratch = nullptr;
+    bool own_scratch = false;
+    ScratchLayout lay{};
+    uint64_t *keys = nullptr;
+    uint32_t *touched = nullptr;
+    DevCounters *ctr = nullptr;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    // host point staging (double-buffered pinned) and its device copy
+    float *pinned[2] = {nullptr, nullptr};
+    hipEvent_t pinned_ev[2] = {nullptr, nullptr};
+    bool pinned_ev_live[2] = {false, false};
+    int pinned_cur = 0;
+    int64_t pinned_cap = 0;  // points
+    float *dev_pts = nullptr;
+    int64_t dev_pts_cap = 0;  // points
+    // shift / readback staging
+    int16_t *stage_dev = nullptr;  // [2][stage_cap]
+    int16_t *stage_host = nullptr;
+    int64_t stage_cap = 0;  // voxels per array
+    BoxXfer *boxes_dev = nullptr;
+    BoxXfer *boxes_host = nullptr;
+    int32_t boxes_cap = 0;
+    // state
+    bool poisoned = false;
+    std::atomic<int> busy{0};
+    std::unordered_map<ChunkKey, Chunk, ChunkKeyHash> store;
+};
+
+namespace {
+
+struct Guard {
+    tsdf_map *m;
+    bool ok;
+    explicit Guard(tsdf_map *mm) : m(mm), ok(false)
+    {
+        int expected = 0;
+        ok = m->busy.compare_exchange_strong(expected, 1);
+    }
+    ~Guard()
+    {
+        if (ok) m->busy.store(0);
+    }
+};
+
+tsdf_status fail_device(tsdf_map *m)
+{
+    if (m) m->poisoned = true;
+    return TSDF_EDEVICE;
+}
+
+#define HIPCHK(m, call)                                  \
+    do {                                                 \
+        if ((call) != hipSuccess) return fail_device(m); \
+    } while (0)
+
+int64_t floor_div64(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    if ((a % b != 0) && (a < 0)) --q;
+    return q;
+}
+
+int64_t floor_mod64(int64_t a, int64_t b) { return a - floor_div64(a, b) * b; }
+
+bool desc_ok(const tsdf_map_desc *d)
+{
+    if (!d) return false;
+    int64_t nv = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (d->dims[a] < 1) return false;
+        nv *= d->dims[a];
+        // every window coordinate must stay representable
+        if ((int64_t)d->origin[a] + d->dims[a] > (int64_t)1 << 30 || (int64_t)d->origin[a] < -((int64_t)1 << 30))
+            return false;
+    }
+    if (nv >= ((int64_t)1 << 31)) return false;
+    if (!(d->voxel_size_m > 0.0) || !isfinite(d->voxel_size_m)) return false;
+    if (d->tau_q10 < 1 || d->tau_q10 > 32767) return false;
+    if (d->w_max < 1 || d->w_max > 32767) return false;
+    return true;
+}
+
+int64_t nvox_of(const tsdf_map_desc *d) { return (int64_t)d->dims[0] * d->dims[1] * d->dims[2]; }
+
+tsdf_status ensure_points(tsdf_map *m, int64_t n, bool host)
+{
+    if (n > m->dev_pts_cap) {
+        int64_t cap = std::max<int64_t>(n, 1 << 16);
+        HIPCHK(m, hipStreamSynchronize(m->stream));
+        if (m->dev_pts) HIPCHK(m, hipFree(m->dev_pts));
+        m->dev_pts = nullptr;
+        m->dev_pts_cap = 0;
+        if (hipMalloc(&m->dev_pts, (size_t)cap * 3 * sizeof(float)) != hipSuccess) return TSDF_ENOMEM;
+        m->dev_pts_cap = cap;
+    }
+    if (host && n > m->pinned_cap) {
+        int64_t cap = std::max<int64_t>(n, 1 << 16);
+        for (int k = 0; k < 2; ++k) {
+            if (m->pinned_ev_live[k]) HIPCHK(m, hipEventSynchronize(m->pinned_ev[k]));
+            m->pinned_ev_live[k] = false;
+            if (m->pinned[k]) HIPCHK(m, hipHostFree(m->pinned[k]));
+            m->pinned[k] = nullptr;
+        }
+        m->pinned_cap = 0;
+        for (int k = 0; k < 2; ++k)
+            if (hipHostMalloc((void **)&m->pinned[k], (size_t)cap * 3 * sizeof(float), hipHostMallocDefault) !=
+                hipSuccess)
+                return TSDF_ENOMEM;
+        m->pinned_cap = cap;
+    }
+    return TSDF_OK;
+}
+
+tsdf_status ensure_stage(tsdf_map *m, int64_t vox, int32_t boxes)
+{
+    if (vox > m->stage_cap) {
+        HIPCHK(m, hipStreamSynchronize(m->stream));
+        if (m->stage_dev) HIPCHK(m, hipFree(m->stage_dev));
+        if (m->stage_host) HIPCHK(m, hipHostFree(m->stage_host));
+        m->stage_dev = nullptr;
+        m->stage_host = nullptr;
+        m->stage_cap = 0;
+        if (hipMalloc(&m->stage_dev, (size_t)vox * 2 * sizeof(int16_t)) != hipSuccess) return TSDF_ENOMEM;
+        if (hipHostMalloc((void **)&m->stage_host, (size_t)vox * 2 * sizeof(int16_t), hipHostMallocDefault) !=
+            hipSuccess)
+            return TSDF_ENOMEM;
+        m->stage_cap = vox;
+    }
+    if (boxes > m->boxes_cap) {
+        HIPCHK(m, hipStreamSynchronize(m->stream));
+        if (m->boxes_dev) HIPCHK(m, hipFree(m->boxes_dev));
+        if (m->boxes_host) HIPCHK(m, hipHostFree(m->boxes_host));
+        m->boxes_dev = nullptr;
+        m->boxes_host = nullptr;
+        m->boxes_cap = 0;
+        if (hipMalloc(&m->boxes_dev, (size_t)boxes * sizeof(BoxXfer)) != hipSuccess) return TSDF_ENOMEM;
+        if (hipHostMalloc((void **)&m->boxes_host, (size_t)boxes * sizeof(BoxXfer), hipHostMallocDefault) !=
+            hipSuccess)
+            return TSDF_ENOMEM;
+        m->boxes_cap = boxes;
+    }
+    return TSDF_OK;
+}
+
+tsdf_status init_map(tsdf_map *m)
+{
+    m->nvox = nvox_of(&m->d);
+    m->scale = 1024.0 / m->d.voxel_size_m;
+    m->lay = ScratchLayout::of(m->nvox);
+    m->keys = (uint64_t *)((char *)m->scratch + m->lay.keys_off);
+    m->touched = (uint32_t *)((char *)m->scratch + m->lay.touched_off);
+    m->ctr = (DevCounters *)((char *)m->scratch + m->lay.counters_off);
+    HIPCHK(m, launch_fill_u64(m->keys, m->nvox, kEmptyKey, m->stream));
+    HIPCHK(m, launch_fill_u32((uint32_t *)m->ctr, sizeof(DevCounters) / 4, 0u, m->stream));
+    for (int k = 0; k < 2; ++k)
+        if (hipEventCreateWithFlags(&m->pinned_ev[k], hipEventDisableTiming) != hipSuccess) return fail_device(m);
+    HIPCHK(m, hipStreamSynchronize(m->stream));
+    return TSDF_OK;
+}
+
+void release(tsdf_map *m)
+{
+    if (!m) return;
+    if (m->stream) (void)hipStreamSynchronize(m->stream);
+    if (m->own_arrays) {
+        if (m->sdf) (void)hipFree(m->sdf);
+        if (m->w) (void)hipFree(m->w);
+    }
+    if (m->own_scratch && m->scratch) (void)hipFree(m->scratch);
+    for (int k = 0; k < 2; ++k) {
+        if (m->pinned[k]) (void)hipHostFree(m->pinned[k]);
+        if (m->pinned_ev[k]) (void)hipEventDestroy(m->pinned_ev[k]);
+    }
+    if (m->dev_pts) (void)hipFree(m->dev_pts);
+    if (m->stage_dev) (void)hipFree(m->stage_dev);
+    if (m->stage_host) (void)hipHostFree(m->stage_host);
+    if (m->boxes_dev) (void)hipFree(m->boxes_dev);
+    if (m->boxes_host) (void)hipHostFree(m->boxes_host);
+    if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
+    delete m;
+}
+
+// Box arithmetic over global voxel coordinates.
+struct Box {
+    int32_t lo[3], hi[3];  // [lo, hi)
+    bool empty() const { return lo[0] >= hi[0] || lo[1] >= hi[1] || lo[2] >= hi[2]; }
+    int64_t count() const { return empty() ? 0 : (int64_t)(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]); }
+};
+
+Box window_box(const int32_t origin[3], const int32_t dims[3])
+{
+    Box b;
+    for (int a = 0; a < 3; ++a) {
+        b.lo[a] = origin[a];
+        b.hi[a] = origin[a] + dims[a];
+    }
+    return b;
+}
+
+Box intersect(const Box &x, const Box &y)
+{
+    Box b;
+    for (int a = 0; a < 3; ++a) {
+        b.lo[a] = std::max(x.lo[a], y.lo[a]);
+        b.hi[a] = std::min(x.hi[a], y.hi[a]);
+    }
+    return b;
+}
+
+// A \ B for two boxes of equal extent, as up to three disjoint boxes.
+std::vector<Box> difference(const Box &A, const Box &B)
+{
+    std::vector<Box> out;
+    Box rest = A;  // the part of A not yet split off
+    for (int a = 0; a < 3; ++a) {
+        // part of rest whose coordinate a is outside [B.lo, B.hi)
+        Box lo_part = rest, hi_part = rest;
+        lo_part.hi[a] = std::min(rest.hi[a], B.lo[a]);
+        hi_part.lo[a] = std::max(rest.lo[a], B.hi[a]);
+        if (!lo_part.empty()) out.push_back(lo_part);
+        if (!hi_part.empty()) out.push_back(hi_part);
+        rest.lo[a] = std::max(rest.lo[a], B.lo[a]);
+        rest.hi[a] = std::min(rest.hi[a], B.hi[a]);
+        if (rest.empty()) break;
+    }
+    return out;
+}
+
+// Split a box along the global 64-voxel chunk grid.
+void chunk_pieces(const Box &b, std::vector<Box> &out)
+{
+    if (b.empty()) return;
+    for (int64_t cx = floor_div64(b.lo[0], kChunk); cx * kChunk < b.hi[0]; ++cx)
+        for (int64_t cy = floor_div64(b.lo[1], kChunk); cy * kChunk < b.hi[1]; ++cy)
+            for (int64_t cz = floor_div64(b.lo[2], kChunk); cz * kChunk < b.hi[2]; ++cz) {
+                Box p;
+                const int64_t c[3] = {cx, cy, cz};
+                for (int a = 0; a < 3; ++a) {
+                    p.lo[a] = (int32_t)std::max<int64_t>(b.lo[a], c[a] * kChunk);
+                    p.hi[a] = (int32_t)std::min<int64_t>(b.hi[a], (c[a] + 1) * kChunk);
+                }
+                if (!p.empty()) out.push_back(p);
+            }
+}
+
+ChunkKey key_of(const int32_t g[3])
+{
+    return ChunkKey{(int32_t)floor_div64(g[0], kChunk), (int32_t)floor_div64(g[1], kChunk),
+                    (int32_t)floor_div64(g[2], kChunk)};
+}
+
+inline int64_t chunk_off(int32_t x, int32_t y, int32_t z)
+{
+    return ((int64_t)floor_mod64(x, kChunk) * kChunk + floor_mod64(y, kChunk)) * kChunk + floor_mod64(z, kChunk);
+}
+
+// Run `fn(pieces_batch, staged_total)` over batches of chunk pieces whose
+// total size fits the staging buffers; pieces are staged back to back.
+template <class Fn>
+tsdf_status for_batches(tsdf_map *m, const std::vector<Box> &pieces, Fn fn)
+{
+    const int64_t cap = std::max<int64_t>(m->stage_cap, 16 * kChunkVox);
+    tsdf_status st0 = ensure_stage(m, cap, 4096);
+    if (st0 != TSDF_OK) return st0;
+    size_t i = 0;
+    while (i < pieces.size()) {
+        std::vector<Box> batch;
+        int64_t total = 0;
+        while (i < pieces.size() && (batch.empty() || total + pieces[i].count() <= cap) &&
+               batch.size() < (size_t)4096) {
+            total += pieces[i].count();
+            batch.push_back(pieces[i]);
+            ++i;
+        }
+        int64_t off = 0, maxv = 0;
+        for (size_t k = 0; k < batch.size(); ++k) {
+            BoxXfer &x = m->boxes_host[k];
+            for (int a = 0; a < 3; ++a) {
+                x.lo[a] = batch[k].lo[a];
+                x.ext[a] = batch[k].hi[a] - batch[k].lo[a];
+            }
+            x.off = off;
+            off += batch[k].count();
+            maxv = std::max(maxv, batch[k].count());
+        }
+        tsdf_status st = fn(batch, (int32_t)batch.size(), off, maxv);
+        if (st != TSDF_OK) return st;
+    }
+    return TSDF_OK;
+}
+
+// Device -> host: pieces of the window into host arrays via staging.
+tsdf_status stage_out(tsdf_map *m, int32_t nb, int64_t total, int64_t maxv, bool clear)
+{
+    int16_t *dsdf = m->stage_dev, *dw = m->stage_dev + m->stage_cap;
+    HIPCHK(m, hipMemcpyAsync(m->boxes_dev, m->boxes_host, (size_t)nb * sizeof(BoxXfer), hipMemcpyHostToDevice,
+                             m->stream));
+    HIPCHK(m, launch_pack_boxes(m->boxes_dev, nb, maxv, m->sdf, m->w, m->d.dims, dsdf, dw, clear, m->stream));
+    HIPCHK(m, hipMemcpyAsync(m->stage_host, dsdf, (size_t)total * sizeof(int16_t), hipMemcpyDeviceToHost,
+                             m->stream));
+    HIPCHK(m, hipMemcpyAsync(m->stage_host + m->stage_cap, dw, (size_t)total * sizeof(int16_t),
+                             hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(m, hipStreamSynchronize(m->stream));
+    return TSDF_OK;
+}
+
+bool all_zero(const int16_t *a, const int16_t *b, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (a[i] | b[i]) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tsdf_status_string(tsdf_status s)
+{
+    switch (s) {
+    case TSDF_OK: return "ok";
+    case TSDF_EINVAL: return "invalid argument";
+    case TSDF_ENOMEM: return "out of memory";
+    case TSDF_EDEVICE: return "device error (map poisoned)";
+    case TSDF_ERANGE: return "size out of range";
+    case TSDF_EBUSY: return "map busy";
+    }
+    return "unknown status";
+}
+
+size_t tsdf_scratch_bytes(const tsdf_map_desc *d)
+{
+    if (!desc_ok(d)) return 0;
+    return ScratchLayout::of(nvox_of(d)).total;
+}
+
+tsdf_status tsdf_map_create(const tsdf_map_desc *d, void *hip_stream, tsdf_map **out)
+{
+    if (!desc_ok(d) || !out) return TSDF_EINVAL;
+    *out = nullptr;
+    tsdf_map *m = new (std::nothrow) tsdf_map();
+    if (!m) return TSDF_ENOMEM;
+    m->d = *d;
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        delete m;
+        return TSDF_EDEVICE;
+    }
+    if (hip_stream) {
+        m->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete m;
+            return TSDF_EDEVICE;
+        }
+        m->own_stream = true;
+    }
+    const int64_t nv = nvox_of(d);
+    m->own_arrays = true;
+    m->own_scratch = true;
+    if (hipMalloc(&m->sdf, (size_t)nv * sizeof(int16_t)) != hipSuccess ||
+        hipMalloc(&m->w, (size_t)nv * sizeof(int16_t)) != hipSuccess ||
+        hipMalloc(&m->scratch, ScratchLayout::of(nv).total) != hipSuccess) {
+        release(m);
+        return TSDF_ENOMEM;
+    }
+    if (hipMemsetAsync(m->sdf, 0, (size_t)nv * sizeof(int16_t), m->stream) != hipSuccess ||
+        hipMemsetAsync(m->w, 0, (size_t)nv * sizeof(int16_t), m->stream) != hipSuccess) {
+        release(m);
+        return TSDF_EDEVICE;
+    }
+    tsdf_status st = init_map(m);
+    if (st != TSDF_OK) {
+        release(m);
+        return st;
+    }
+    *out = m;
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_map_create_in(const tsdf_map_desc *d, void *sdf_dev, void *w_dev, void *scratch_dev,
+                               size_t scratch_bytes, void *hip_stream, tsdf_map **out)
+{
+    if (!desc_ok(d) || !out || !sdf_dev || !w_dev || !scratch_dev) return TSDF_EINVAL;
+    if (scratch_bytes < tsdf_scratch_bytes(d)) return TSDF_EINVAL;
+    *out = nullptr;
+    tsdf_map *m = new (std::nothrow) tsdf_map();
+    if (!m) return TSDF_ENOMEM;
+    m->d = *d;
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        delete m;
+        return TSDF_EDEVICE;
+    }
+    if (hip_stream) {
+        m->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete m;
+            return TSDF_EDEVICE;
+        }
+        m->own_stream = true;
+    }
+    m->sdf = (int16_t *)sdf_dev;
+    m->w = (int16_t *)w_dev;
+    m->scratch = scratch_dev;
+    tsdf_status st = init_map(m);
+    if (st != TSDF_OK) {
+        release(m);
+        return st;
+    }
+    *out = m;
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_map_destroy(tsdf_map *m)
+{
+    if (!m) return TSDF_EINVAL;
+    release(m);
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_integrate_scan(tsdf_map *m, const float *xyz, int64_t n_points, tsdf_ptr_kind kind,
+                                const double pose[16], tsdf_scan_stats *stats)
+{
+    if (!m || !pose || n_points < 0 || n_points > 0xffffffffLL || (n_points > 0 && !xyz)) return TSDF_EINVAL;
+    if (kind != TSDF_PTR_HOST && kind != TSDF_PTR_DEVICE) return TSDF_EINVAL;
+    Guard g(m);
+    if (!g.ok) return TSDF_EBUSY;
+    if (m->poisoned) return TSDF_EDEVICE;
+    ScanParams P;
+    for (int k = 0; k < 12; ++k) {
+        if (!isfinite(pose[k])) return TSDF_EINVAL;
+        P.M[k] = pose[k];
+    }
+    P.scale = m->scale;
+    for (int a = 0; a < 3; ++a) {
+        const double r = nearbyint(pose[4 * a + 3] * m->scale);
+        if (!(fabs(r) < 1073741824.0)) return TSDF_EINVAL;
+        P.o[a] = (int32_t)r;
+        P.dims[a] = m->d.dims[a];
+        P.origin[a] = m->d.origin[a];
+        P.ring0[a] = (int32_t)floor_mod64(m->d.origin[a], m->d.dims[a]);
+    }
+    P.tau = m->d.tau_q10;
+    P.pad = 0;
+    P.n = n_points;
+    P.xyz = xyz;
+    if (kind == TSDF_PTR_HOST && n_points > 0) {
+        tsdf_status st = ensure_points(m, n_points, true);
+        if (st != TSDF_OK) return st;
+        const int k = m->pinned_cur;
+        if (m->pinned_ev_live[k]) HIPCHK(m, hipEventSynchronize(m->pinned_ev[k]));
+        memcpy(m->pinned[k], xyz, (size_t)n_points * 3 * sizeof(float));
+        HIPCHK(m, hipMemcpyAsync(m->dev_pts, m->pinned[k], (size_t)n_points * 3 * sizeof(float),
+                                 hipMemcpyHostToDevice, m->stream));
+        HIPCHK(m, hipEventRecord(m->pinned_ev[k], m->stream));
+        m->pinned_ev_live[k] = true;
+        m->pinned_cur ^= 1;
+        P.xyz = m->dev_pts;
+    }
+    HIPCHK(m, launch_integrate_plain(P, m->keys, m->touched, m->ctr, m->sdf, m->w, m->d.w_max, m->stream));
+    if (stats) {
+        uint32_t last[4];
+        HIPCHK(m, hipMemcpyAsync(last, m->ctr->last, sizeof(last), hipMemcpyDeviceToHost, m->stream));
+        HIPCHK(m, hipStreamSynchronize(m->stream));
+        stats->points_in = n_points;
+        stats->points_valid = last[1];
+        stats->visits = last[2];
+        stats->voxels_updated = last[0];
+    }
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_shift(tsdf_map *m, const int32_t new_origin[3])
+{
+    if (!m || !new_origin) return TSDF_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if ((int64_t)new_origin[a] + m->d.dims[a] > (int64_t)1 << 30 || (int64_t)new_origin[a] < -((int64_t)1 << 30))
+            return TSDF_EINVAL;
+    Guard g(m);
+    if (!g.ok) return TSDF_EBUSY;
+    if (m->poisoned) return TSDF_EDEVICE;
+    const Box oldw = window_box(m->d.origin, m->d.dims);
+    const Box neww = window_box(new_origin, m->d.dims);
+    std::vector<Box> leaving, entering, lp, ep;
+    leaving = difference(oldw, neww);
+    entering = difference(neww, oldw);
+    for (auto &b : leaving) chunk_pieces(b, lp);
+    for (auto &b : entering) chunk_pieces(b, ep);
+
+    // 1. leaving voxels: pack (and clear their slots) -> host -> store
+    tsdf_status st = for_batches(m, lp, [&](const std::vector<Box> &batch, int32_t nb, int64_t total, int64_t maxv) {
+        tsdf_status s = stage_out(m, nb, total, maxv, true);
+        if (s != TSDF_OK) return s;
+        const int16_t *hs = m->stage_host, *hw = m->stage_host + m->stage_cap;
+        for (int32_t k = 0; k < nb; ++k) {
+            const Box &b = batch[k];
+            const int64_t off = m->boxes_host[k].off;
+            const int64_t cnt = b.count();
+            const ChunkKey ck = key_of(b.lo);
+            auto it = m->store.find(ck);
+            if (it == m->store.end()) {
+                if (all_zero(hs + off, hw + off, cnt)) continue;  // nothing observed: nothing to keep
+                Chunk c;
+                c.sdf.assign(kChunkVox, 0);
+                c.w.assign(kChunkVox, 0);
+                it = m->store.emplace(ck, std::move(c)).first;
+            }
+            Chunk &c = it->second;
+            const int32_t ey = b.hi[1] - b.lo[1], ez = b.hi[2] - b.lo[2];
+            for (int32_t x = b.lo[0]; x < b.hi[0]; ++x)
+                for (int32_t y = b.lo[1]; y < b.hi[1]; ++y) {
+                    const int64_t src = off + ((int64_t)(x - b.lo[0]) * ey + (y - b.lo[1])) * ez;
+                    const int64_t dst = chunk_off(x, y, b.lo[2]);
+                    memcpy(&c.sdf[dst], hs + src, (size_t)ez * sizeof(int16_t));
+                    memcpy(&c.w[dst], hw + src, (size_t)ez * sizeof(int16_t));
+                }
+        }
+        return TSDF_OK;
+    });
+    if (st != TSDF_OK) return st;
+
+    // 2. entering voxels held by the store: store -> host staging -> unpack
+    std::vector<Box> present;
+    for (auto &b : ep)
+        if (m->store.count(key_of(b.lo))) present.push_back(b);
+    st = for_batches(m, present, [&](const std::vector<Box> &batch, int32_t nb, int64_t total, int64_t maxv) {
+        int16_t *hs = m->stage_host, *hw = m->stage_host + m->stage_cap;
+        for (int32_t k = 0; k < nb; ++k) {
+            const Box &b = batch[k];
+            const int64_t off = m->boxes_host[k].off;
+            auto it = m->store.find(key_of(b.lo));
+            Chunk &c = it->second;
+            const int32_t ey = b.hi[1] - b.lo[1], ez = b.hi[2] - b.lo[2];
+            for (int32_t x = b.lo[0]; x < b.hi[0]; ++x)
+                for (int32_t y = b.lo[1]; y < b.hi[1]; ++y) {
+                    const int64_t dst = off + ((int64_t)(x - b.lo[0]) * ey + (y - b.lo[1])) * ez;
+                    const int64_t src = chunk_off(x, y, b.lo[2]);
+                    memcpy(hs + dst, &c.sdf[src], (size_t)ez * sizeof(int16_t));
+                    memcpy(hw + dst, &c.w[src], (size_t)ez * sizeof(int16_t));
+                    // popped: the store no longer holds these voxels
+                    memset(&c.sdf[src], 0, (size_t)ez * sizeof(int16_t));
+                    memset(&c.w[src], 0, (size_t)ez * sizeof(int16_t));
+                }
+            if (b.count() == kChunkVox) m->store.erase(it);
+        }
+        int16_t *dsdf = m->stage_dev, *dw = m->stage_dev + m->stage_cap;
+        HIPCHK(m, hipMemcpyAsync(m->boxes_dev, m->boxes_host, (size_t)nb * sizeof(BoxXfer), hipMemcpyHostToDevice,
+                                 m->stream));
+        HIPCHK(m, hipMemcpyAsync(dsdf, hs, (size_t)total * sizeof(int16_t), hipMemcpyHostToDevice, m->stream));
+        HIPCHK(m, hipMemcpyAsync(dw, hw, (size_t)total * sizeof(int16_t), hipMemcpyHostToDevice, m->stream));
+        HIPCHK(m, launch_unpack_boxes(m->boxes_dev, nb, maxv, m->sdf, m->w, m->d.dims, dsdf, dw, m->stream));
+        HIPCHK(m, hipStreamSynchronize(m->stream));
+        return TSDF_OK;
+    });
+    if (st != TSDF_OK) return st;
+    for (int a = 0; a < 3; ++a) m->d.origin[a] = new_origin[a];
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_readback(tsdf_map *m, const int32_t lo[3], const int32_t hi[3], int16_t *sdf_out, int16_t *w_out)
+{
+    if (!m || !lo || !hi || !sdf_out || !w_out) return TSDF_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (hi[a] < lo[a]) return TSDF_EINVAL;
+    Guard g(m);
+    if (!g.ok) return TSDF_EBUSY;
+    if (m->poisoned) return TSDF_EDEVICE;
+    Box req;
+    for (int a = 0; a < 3; ++a) {
+        req.lo[a] = lo[a];
+        req.hi[a] = hi[a];
+    }
+    if (req.empty()) return TSDF_OK;
+    const int64_t ny = hi[1] - lo[1], nz = hi[2] - lo[2];
+    // stored or unseen voxels first
+    std::vector<Box> pieces;
+    chunk_pieces(req, pieces);
+    for (const Box &b : pieces) {
+        auto it = m->store.find(key_of(b.lo));
+        for (int32_t x = b.lo[0]; x < b.hi[0]; ++x)
+            for (int32_t y = b.lo[1]; y < b.hi[1]; ++y) {
+                const int64_t dst = ((int64_t)(x - lo[0]) * ny + (y - lo[1])) * nz + (b.lo[2] - lo[2]);
+                const size_t nb = (size_t)(b.hi[2] - b.lo[2]) * sizeof(int16_t);
+                if (it == m->store.end()) {
+                    memset(sdf_out + dst, 0, nb);
+                    memset(w_out + dst, 0, nb);
+                } else {
+                    const int64_t src = chunk_off(x, y, b.lo[2]);
+                    memcpy(sdf_out + dst, &it->second.sdf[src], nb);
+                    memcpy(w_out + dst, &it->second.w[src], nb);
+                }
+            }
+    }
+    // then the resident part, from the device
+    const Box res = intersect(req, window_box(m->d.origin, m->d.dims));
+    std::vector<Box> rp;
+    chunk_pieces(res, rp);
+    return for_batches(m, rp, [&](const std::vector<Box> &batch, int32_t nb, int64_t total, int64_t maxv) {
+        tsdf_status s = stage_out(m, nb, total, maxv, false);
+        if (s != TSDF_OK) return s;
+        const int16_t *hs = m->stage_host, *hw = m->stage_host + m->stage_cap;
+        for (int32_t k = 0; k < nb; ++k) {
+            const Box &b = batch[k];
+            const int64_t off = m->boxes_host[k].off;
+            const int32_t ey = b.hi[1] - b.lo[1], ez = b.hi[2] - b.lo[2];
+            for (int32_t x = b.lo[0]; x < b.hi[0]; ++x)
+                for (int32_t y = b.lo[1]; y < b.hi[1]; ++y) {
+                    const int64_t src = off + ((int64_t)(x - b.lo[0]) * ey + (y - b.lo[1])) * ez;
+                    const int64_t dst = ((int64_t)(x - lo[0]) * ny + (y - lo[1])) * nz + (b.lo[2] - lo[2]);
+                    memcpy(sdf_out + dst, hs + src, (size_t)ez * sizeof(int16_t));
+                    memcpy(w_out + dst, hw + src, (size_t)ez * sizeof(int16_t));
+                }
+        }
+        return TSDF_OK;
+    });
+}
+
+tsdf_status tsdf_integrate_batch(const tsdf_scan_desc *scans, int32_t count, tsdf_ptr_kind kind, void *hip_stream,
+                                 tsdf_scan_stats *stats)
+{
+    (void)hip_stream;
+    if (count < 0 || (count > 0 && !scans)) return TSDF_EINVAL;
+    for (int32_t k = 0; k < count; ++k) {
+        tsdf_status st = tsdf_integrate_scan(scans[k].map, scans[k].xyz, scans[k].n_points, kind, scans[k].pose,
+                                             stats ? &stats[k] : nullptr);
+        if (st != TSDF_OK) return st;
+    }
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_map_origin(const tsdf_map *m, int32_t origin[3])
+{
+    if (!m || !origin) return TSDF_EINVAL;
+    for (int a = 0; a < 3; ++a) origin[a] = m->d.origin[a];
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_map_device_arrays(const tsdf_map *m, void **sdf_dev, void **w_dev, void **hip_stream)
+{
+    if (!m) return TSDF_EINVAL;
+    if (sdf_dev) *sdf_dev = m->sdf;
+    if (w_dev) *w_dev = m->w;
+    if (hip_stream) *hip_stream = m->stream;
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_recentre_origin(const tsdf_map *m, const double pose[16], int64_t radius_q10, int32_t chunk,
+                                 int32_t force, int32_t new_origin[3], int32_t *due)
+{
+    if (!m || !pose || !new_origin || !due || chunk < 1 || radius_q10 < 0) return TSDF_EINVAL;
+    int64_t o[3];
+    for (int a = 0; a < 3; ++a) {
+        const double r = nearbyint(pose[4 * a + 3] * m->scale);
+        if (!(fabs(r) < 1073741824.0)) return TSDF_EINVAL;
+        o[a] = (int64_t)r;
+    }
+    __int128 d2 = 0;
+    for (int a = 0; a < 3; ++a) {
+        const __int128 c = (__int128)1024 * ((int64_t)m->d.origin[a] + m->d.dims[a] / 2);
+        const __int128 dd = (__int128)o[a] - c;
+        d2 += dd * dd;
+    }
+    *due = (force || d2 > (__int128)radius_q10 * radius_q10) ? 1 : 0;
+    for (int a = 0; a < 3; ++a) {
+        const int64_t sv = floor_div64(o[a], 1024);
+        new_origin[a] = (int32_t)(chunk * floor_div64(sv + chunk / 2, chunk) - m->d.dims[a] / 2);
+    }
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_store_info(const tsdf_map *m, int64_t *chunks, int64_t *bytes)
+{
+    if (!m) return TSDF_EINVAL;
+    if (chunks) *chunks = (int64_t)m->store.size();
+    if (bytes) *bytes = (int64_t)m->store.size() * kChunkVox * 2 * (int64_t)sizeof(int16_t);
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_map_synchronize(tsdf_map *m)
+{
+    if (!m) return TSDF_EINVAL;
+    if (m->poisoned) return TSDF_EDEVICE;
+    HIPCHK(m, hipStreamSynchronize(m->stream));
+    return TSDF_OK;
+}
+
+}  // extern "C"

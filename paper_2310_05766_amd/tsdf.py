@@ -1,0 +1,181 @@
+"""Python face of the C ABI: one object per map, same call names.
+
+Argument marshalling only -- every step of integration, shift and readback
+runs in the HIP library. Host arrays are numpy; device arrays are torch
+tensors (torch provides device memory and streams).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _abi
+from ._abi import check
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+def _pose_arg(pose):
+    M = np.ascontiguousarray(np.asarray(pose, dtype=np.float64).reshape(16))
+    return M, M.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _points_arg(xyz):
+    """(pointer, n, kind, keepalive) for a numpy host array or a torch device tensor."""
+    if isinstance(xyz, np.ndarray):
+        a = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+        return a.ctypes.data, a.shape[0], _abi.TSDF_PTR_HOST, a
+    # torch tensor
+    if xyz.dtype.__str__() != "torch.float32" or not xyz.is_contiguous() or xyz.dim() != 2 or xyz.shape[1] != 3:
+        raise ValueError("device points must be a contiguous float32 tensor of shape (n, 3)")
+    if not xyz.is_cuda:
+        a = xyz.numpy()
+        return a.ctypes.data, a.shape[0], _abi.TSDF_PTR_HOST, a
+    return xyz.data_ptr(), xyz.shape[0], _abi.TSDF_PTR_DEVICE, xyz
+
+
+class TsdfMap:
+    """A TSDF window (int16 SDF + int16 weight per voxel) plus its host chunk store."""
+
+    def __init__(self, dims, origin, voxel_size, tau_u, w_max, stream=None, arrays=None):
+        self.desc = _abi.MapDesc((C.c_int32 * 3)(*[int(v) for v in dims]), (C.c_int32 * 3)(*[int(v) for v in origin]),
+                                 float(voxel_size), int(tau_u), int(w_max))
+        self.dims = tuple(int(v) for v in dims)
+        self.voxel_size = float(voxel_size)
+        self.tau_u, self.w_max = int(tau_u), int(w_max)
+        self._h = C.c_void_p()
+        self._keep = None
+        L = _abi.lib()
+        sh = _stream_handle(stream)
+        if arrays is None:
+            check(L.tsdf_map_create(C.byref(self.desc), sh, C.byref(self._h)), "tsdf_map_create")
+        else:
+            sdf, w, scratch = arrays  # caller-owned torch tensors
+            self._keep = arrays
+            check(L.tsdf_map_create_in(C.byref(self.desc), sdf.data_ptr(), w.data_ptr(), scratch.data_ptr(),
+                                       scratch.numel() * scratch.element_size(), sh, C.byref(self._h)),
+                  "tsdf_map_create_in")
+
+    @staticmethod
+    def scratch_bytes(dims, origin, voxel_size, tau_u, w_max) -> int:
+        d = _abi.MapDesc((C.c_int32 * 3)(*dims), (C.c_int32 * 3)(*origin), float(voxel_size), int(tau_u), int(w_max))
+        return int(_abi.lib().tsdf_scratch_bytes(C.byref(d)))
+
+    @classmethod
+    def from_spec(cls, spec, origin=None, stream=None):
+        return cls(spec.dims, spec.origin if origin is None else origin, spec.voxel_size, spec.tau_u, spec.w_max,
+                   stream=stream)
+
+    @property
+    def handle(self):
+        return self._h.value
+
+    def close(self):
+        if self._h:
+            check(_abi.lib().tsdf_map_destroy(self._h), "tsdf_map_destroy")
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def integrate(self, xyz, pose, stats: bool = False):
+        """tsdf_integrate_scan. With stats=True waits and returns the counts."""
+        ptr, n, kind, _keep = _points_arg(xyz)
+        _M, Mp = _pose_arg(pose)
+        st = _abi.ScanStats() if stats else None
+        check(_abi.lib().tsdf_integrate_scan(self._h, ptr, n, kind, Mp, C.byref(st) if stats else None),
+              "tsdf_integrate_scan")
+        if stats:
+            return dict(points_in=st.points_in, points_valid=st.points_valid, visits=st.visits,
+                        voxels_updated=st.voxels_updated)
+        return None
+
+    def shift(self, new_origin):
+        o = (C.c_int32 * 3)(*[int(v) for v in new_origin])
+        check(_abi.lib().tsdf_shift(self._h, o), "tsdf_shift")
+
+    def readback(self, lo, hi):
+        lo_ = (C.c_int32 * 3)(*[int(v) for v in lo])
+        hi_ = (C.c_int32 * 3)(*[int(v) for v in hi])
+        shape = tuple(int(h) - int(l) for l, h in zip(lo, hi))
+        sdf = np.zeros(shape, dtype=np.int16)
+        w = np.zeros(shape, dtype=np.int16)
+        check(_abi.lib().tsdf_readback(self._h, lo_, hi_, sdf.ctypes.data_as(C.POINTER(C.c_int16)),
+                                       w.ctypes.data_as(C.POINTER(C.c_int16))), "tsdf_readback")
+        return sdf, w
+
+    def readback_window(self):
+        o = self.origin
+        return self.readback(o, tuple(o[a] + self.dims[a] for a in range(3)))
+
+    @property
+    def origin(self):
+        o = (C.c_int32 * 3)()
+        check(_abi.lib().tsdf_map_origin(self._h, o), "tsdf_map_origin")
+        return tuple(int(v) for v in o)
+
+    def device_arrays(self):
+        s, w, st = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        check(_abi.lib().tsdf_map_device_arrays(self._h, C.byref(s), C.byref(w), C.byref(st)),
+              "tsdf_map_device_arrays")
+        return s.value, w.value, st.value
+
+    def recentre_origin(self, pose, radius_q10: int, chunk: int = 64, force: bool = False):
+        _M, Mp = _pose_arg(pose)
+        out = (C.c_int32 * 3)()
+        due = C.c_int32(0)
+        check(_abi.lib().tsdf_recentre_origin(self._h, Mp, int(radius_q10), int(chunk), int(bool(force)), out,
+                                              C.byref(due)), "tsdf_recentre_origin")
+        return bool(due.value), tuple(int(v) for v in out)
+
+    def store_info(self):
+        c, b = C.c_int64(), C.c_int64()
+        check(_abi.lib().tsdf_store_info(self._h, C.byref(c), C.byref(b)), "tsdf_store_info")
+        return int(c.value), int(b.value)
+
+    def synchronize(self):
+        check(_abi.lib().tsdf_map_synchronize(self._h), "tsdf_map_synchronize")
+
+
+def integrate_batch(items, stream=None, stats: bool = False):
+    """tsdf_integrate_batch over [(TsdfMap, xyz, pose), ...]; scans sharing a
+    map are applied in list order. All points must be of one kind."""
+    n = len(items)
+    arr = (_abi.ScanDesc * max(n, 1))()
+    keep = []
+    kinds = set()
+    for k, (m, xyz, pose) in enumerate(items):
+        ptr, npts, kind, kp = _points_arg(xyz)
+        keep.append(kp)
+        kinds.add(kind)
+        arr[k].map = m.handle
+        arr[k].xyz = ptr
+        arr[k].n_points = npts
+        M = np.asarray(pose, dtype=np.float64).reshape(16)
+        for j in range(16):
+            arr[k].pose[j] = float(M[j])
+    if len(kinds) > 1:
+        raise ValueError("a batch takes host points or device points, not both")
+    kind = kinds.pop() if kinds else _abi.TSDF_PTR_HOST
+    st = (_abi.ScanStats * max(n, 1))() if stats else None
+    check(_abi.lib().tsdf_integrate_batch(arr, n, kind, _stream_handle(stream), st), "tsdf_integrate_batch")
+    if stats:
+        return [dict(points_in=s.points_in, points_valid=s.points_valid, visits=s.visits,
+                     voxels_updated=s.voxels_updated) for s in st[:n]]
+    return None

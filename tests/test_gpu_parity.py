@@ -1,0 +1,325 @@
+"""GPU parity: the HIP library (through the C ABI) against the oracle,
+bit-exact, on the same seeded inputs."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle_runs
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_map(dims, origin, vs, tau, wmax):
+    from paper_2310_05766_amd.tsdf import TsdfMap
+    return TsdfMap(dims, origin, vs, tau, wmax)
+
+
+def window_box(origin, dims):
+    return tuple(origin), tuple(origin[a] + dims[a] for a in range(3))
+
+
+def assert_same_window(gm, om, dims):
+    o = gm.origin
+    lo, hi = window_box(o, dims)
+    g_sdf, g_w = gm.readback(lo, hi)
+    o_sdf, o_w = om.readback(lo, hi)
+    bad = np.argwhere((g_sdf != o_sdf) | (g_w != o_w))
+    assert bad.shape[0] == 0, (
+        f"{bad.shape[0]} voxels differ; first {bad[:5].tolist()} gpu {[(int(g_sdf[tuple(b)]), int(g_w[tuple(b)])) for b in bad[:5]]} "
+        f"oracle {[(int(o_sdf[tuple(b)]), int(o_w[tuple(b)])) for b in bad[:5]]}")
+    return int((g_w > 0).sum())
+
+
+# -- config 1 -----------------------------------------------------------------
+
+def test_config1_bit_exact():
+    w = synth.config1()
+    spec = w.maps[0]
+    sc = w.scans[0]
+    say("config1", spec)
+    om = oracle.OracleMap.from_spec(spec)
+    ost = om.integrate(sc.xyz, sc.pose)
+    gm = gpu_map(spec.dims, spec.origin, spec.voxel_size, spec.tau_u, spec.w_max)
+    gst = gm.integrate(sc.xyz, sc.pose, stats=True)
+    assert gst == ost
+    seen = assert_same_window(gm, om, spec.dims)
+    assert seen == ost["voxels_updated"] > 10000
+    # a second and third scan of the same points from other poses: merge path
+    for k in range(2):
+        pose = synth.fuzz_pose(900 + k, max_t=0.5)
+        assert gm.integrate(sc.xyz, pose, stats=True) == om.integrate(sc.xyz, pose)
+    assert_same_window(gm, om, spec.dims)
+    gm.close()
+    om.close()
+
+
+def test_plane_profile_golden_gpu():
+    d = json.load(open(os.path.join(GOLDEN, "plane_profile.json")))
+    for side in ("plus_x", "minus_x"):
+        prof = d[side]
+        gm = gpu_map((64, 8, 8), (0, 0, 0), d["voxel_size_m"], d["tau_u"], d["w_max"])
+        for j, k in [(0, 0), (2, 5)]:
+            pose = np.eye(4)
+            pose[:3, 3] = [prof["sensor_m"][0], prof["sensor_m"][1] + j, prof["sensor_m"][2] + k]
+            gm.integrate(np.array([prof["point_sensor_m"]], dtype=np.float32), pose)
+        sdf, w = gm.readback((0, 0, 0), (64, 8, 8))
+        for j, k in [(0, 0), (2, 5)]:
+            xs = np.nonzero(w[:, j, k])[0].tolist()
+            assert xs == prof["voxels_x"]
+            assert sdf[xs, j, k].tolist() == prof["sdf"]
+        assert int(w.sum()) == 2 * len(prof["voxels_x"])
+        gm.close()
+
+
+# -- randomised small maps ----------------------------------------------------
+
+FUZZ = [
+    # dims, origin, voxel, tau, w_max, extent, nan_frac, snap, n, scans
+    ((37, 20, 9), (-18, -10, -4), 0.1, 1536, 64, 1.5, 0.05, None, 3000, 3),
+    ((16, 16, 16), (-8, -8, -8), 0.05, 3072, 3, 0.6, 0.1, 0.025, 4000, 6),
+    ((64, 33, 17), (3, -40, -9), 0.08, 5120, 64, 4.0, 0.0, None, 5000, 3),
+    ((1, 1, 1), (0, 0, 0), 0.2, 3072, 64, 1.0, 0.0, None, 2000, 2),
+    ((128, 2, 64), (-64, -1, -32), 0.05, 1024, 10, 3.5, 0.02, 0.05, 6000, 4),
+    ((50, 50, 50), (-25, -25, -25), 0.064, 32767, 64, 2.0, 0.01, None, 3000, 2),
+    ((40, 40, 40), (-20, -20, -20), 0.05, 1, 64, 1.0, 0.0, 0.05, 3000, 2),
+    ((20, 30, 40), (-1000, 500, -7), 0.05, 3072, 64, 60.0, 0.0, None, 4000, 2),
+]
+
+
+@pytest.mark.parametrize("case", range(len(FUZZ)))
+def test_fuzz_small_maps(case):
+    dims, origin, vs, tau, wmax, extent, nanf, snap, n, nscans = FUZZ[case]
+    say("fuzz case", case, FUZZ[case])
+    om = oracle.OracleMap(dims, origin, vs, tau, wmax)
+    gm = gpu_map(dims, origin, vs, tau, wmax)
+    for k in range(nscans):
+        xyz = synth.fuzz_scan((case, k), n, extent_m=extent, nan_frac=nanf, grid_snap=snap)
+        pose = synth.fuzz_pose((case, k, 7), max_t=0.3 * extent)
+        if snap and k == 0:
+            pose = np.eye(4)
+            pose[:3, 3] = np.round(pose[:3, 3] / snap) * snap
+        gst = gm.integrate(xyz, pose, stats=True)
+        ost = om.integrate(xyz, pose)
+        assert gst == ost, (k, gst, ost)
+    assert_same_window(gm, om, dims)
+    gm.close()
+    om.close()
+
+
+def test_heavy_contention_ties_lowest_index():
+    """Thousands of copies of a few points: every voxel has many equal keys
+    except for the point index; the lowest index must win."""
+    base = synth.fuzz_scan(5, 12, extent_m=0.5, nan_frac=0.0)
+    xyz = np.tile(base, (3000, 1))
+    dims, origin = (32, 32, 32), (-16, -16, -16)
+    om = oracle.OracleMap(dims, origin, 0.05, 3072, 64)
+    gm = gpu_map(dims, origin, 0.05, 3072, 64)
+    pose = synth.fuzz_pose(6, 0.1)
+    assert gm.integrate(xyz, pose, stats=True) == om.integrate(xyz, pose)
+    # reversed order gives a different winner index but, for identical
+    # points, the same values
+    assert_same_window(gm, om, dims)
+    gm.close()
+    om.close()
+
+
+def test_repeatable_across_runs():
+    w = synth.config1()
+    sc = w.scans[0]
+    spec = w.maps[0]
+    outs = []
+    for _ in range(2):
+        gm = gpu_map(spec.dims, spec.origin, spec.voxel_size, spec.tau_u, spec.w_max)
+        gm.integrate(sc.xyz, sc.pose)
+        gm.integrate(sc.xyz, synth.fuzz_pose(3, 0.3))
+        outs.append(gm.readback_window())
+        gm.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_edge_cases_and_errors():
+    from paper_2310_05766_amd import TsdfError
+    dims, origin = (16, 16, 16), (-8, -8, -8)
+    gm = gpu_map(dims, origin, 0.1, 3072, 64)
+    om = oracle.OracleMap(dims, origin, 0.1, 3072, 64)
+    # empty scan
+    assert gm.integrate(np.zeros((0, 3), np.float32), np.eye(4), stats=True) == \
+        dict(points_in=0, points_valid=0, visits=0, voxels_updated=0)
+    # all no-return, and points exactly at the sensor
+    nanpts = np.full((100, 3), np.nan, np.float32)
+    assert gm.integrate(nanpts, np.eye(4), stats=True)["points_valid"] == 0
+    zero = np.zeros((10, 3), np.float32)
+    assert gm.integrate(zero, np.eye(4), stats=True)["points_valid"] == 0
+    xyz = synth.fuzz_scan(31, 500, extent_m=0.7)
+    pose = synth.fuzz_pose(32, 0.2)
+    gm.integrate(xyz, pose)
+    om.integrate(xyz, pose)
+    before = gm.readback_window()
+    # invalid calls leave the map untouched
+    bad_pose = pose.copy()
+    bad_pose[0, 1] = np.nan
+    with pytest.raises(TsdfError):
+        gm.integrate(xyz, bad_pose)
+    far = pose.copy()
+    far[0, 3] = 1e9  # sensor position not representable
+    with pytest.raises(TsdfError):
+        gm.integrate(xyz, far)
+    after = gm.readback_window()
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    assert_same_window(gm, om, dims)
+    # points far outside the window: rays walked, nothing resident touched
+    st = gm.integrate(np.array([[500.0, 0, 0], [0, -300.0, 2.0]], np.float32), np.eye(4), stats=True)
+    assert st["points_valid"] == 2 and st["visits"] == 0 and st["voxels_updated"] == 0
+    gm.close()
+    om.close()
+
+
+def test_invalid_map_descriptors():
+    from paper_2310_05766_amd import TsdfError
+    for args in [((0, 4, 4), (0, 0, 0), 0.1, 3072, 64), ((4, 4, 4), (0, 0, 0), 0.0, 3072, 64),
+                 ((4, 4, 4), (0, 0, 0), 0.1, 0, 64), ((4, 4, 4), (0, 0, 0), 0.1, 40000, 64),
+                 ((4, 4, 4), (0, 0, 0), 0.1, 3072, 0), ((2048, 2048, 1024), (0, 0, 0), 0.1, 3072, 64)]:
+        with pytest.raises(TsdfError):
+            gpu_map(*args)
+
+
+def test_device_pointer_path_matches_host_path():
+    import torch
+    w = synth.config1()
+    sc = w.scans[0]
+    spec = w.maps[0]
+    a = gpu_map(spec.dims, spec.origin, spec.voxel_size, spec.tau_u, spec.w_max)
+    b = gpu_map(spec.dims, spec.origin, spec.voxel_size, spec.tau_u, spec.w_max)
+    a.integrate(sc.xyz, sc.pose)
+    dev = torch.from_numpy(sc.xyz).to("cuda")
+    torch.cuda.synchronize()
+    sb = b.integrate(dev, sc.pose, stats=True)
+    assert sb["points_in"] == sc.xyz.shape[0]
+    ra, rb = a.readback_window(), b.readback_window()
+    assert np.array_equal(ra[0], rb[0]) and np.array_equal(ra[1], rb[1])
+    a.close()
+    b.close()
+
+
+# -- shift and readback on the GPU --------------------------------------------
+
+def test_shift_matches_oracle_and_inverse_is_identity():
+    dims, origin = (64, 64, 64), (-32, -32, -32)
+    gm = gpu_map(dims, origin, 0.05, 3072, 64)
+    om = oracle.OracleMap(dims, origin, 0.05, 3072, 64)
+    xyz = synth.config1().scans[0].xyz
+    for k, new in enumerate([(32, -32, -32), (0, 0, -32), (5, -7, 3), (-70, 12, -40), (-32, -32, -32)]):
+        pose = synth.fuzz_pose(60 + k, 0.5)
+        pose[:3, 3] += [(new[a] + 32) * 0.05 for a in range(3)]
+        gm.integrate(xyz, pose)
+        om.integrate(xyz, pose)
+        box = ((-200, -200, -200), (200, 200, 200))
+        g_before = gm.readback(*box)
+        gm.shift(new)
+        om.shift(new)
+        g_after = gm.readback(*box)
+        assert np.array_equal(g_before[0], g_after[0]) and np.array_equal(g_before[1], g_after[1])
+        o_after = om.readback(*box)
+        assert np.array_equal(g_after[0], o_after[0]) and np.array_equal(g_after[1], o_after[1])
+        assert gm.origin == tuple(new)
+    gm.close()
+    om.close()
+
+
+# -- config 2: the OS1-128-shaped sequence ------------------------------------
+
+def test_config2_sequence_bit_exact():
+    w = synth.config2()
+    spec = w.maps[0]
+    say("config2", len(w.scans), "scans")
+    om = oracle.OracleMap.from_spec(spec)
+    gm = gpu_map(spec.dims, spec.origin, spec.voxel_size, spec.tau_u, spec.w_max)
+    for k, sc in enumerate(w.scans):
+        gst = gm.integrate(sc.xyz, sc.pose, stats=True)
+        ost = om.integrate(sc.xyz, sc.pose)
+        assert gst == ost, (k, gst, ost)
+    seen = assert_same_window(gm, om, spec.dims)
+    say("config2 voxels observed", seen)
+    gm.close()
+    om.close()
+
+
+# -- config 3: ring buffer around a closed loop -------------------------------
+
+def run_ring(map_obj, scans, recentre):
+    """Drive a map through the recentre rule: before each scan, shift if due."""
+    shifts = 0
+    for sc in scans:
+        due, new = recentre(map_obj, sc.pose)
+        if due:
+            map_obj.shift(new)
+            shifts += 1
+        map_obj.integrate(sc.xyz, sc.pose)
+    return shifts
+
+
+def test_config3_ring_global_map_bit_exact():
+    w = synth.config3()
+    spec = w.maps[0]
+    radius = w.extra["recentre_vox"] * 1024
+    _, o0 = oracle.recentre(spec.dims, (0, 0, 0), spec.voxel_size, w.scans[0].pose, radius, force=True)
+    gm = gpu_map(spec.dims, o0, spec.voxel_size, spec.tau_u, spec.w_max)
+    g_shifts = run_ring(gm, w.scans, lambda m, p: m.recentre_origin(p, radius, 64))
+    say("config3 gpu shifts", g_shifts, "store", gm.store_info())
+    om = oracle.OracleMap.from_spec(spec, origin=o0)
+    state = {"o": o0}
+
+    def orc(m, p):
+        due, new = oracle.recentre(spec.dims, state["o"], spec.voxel_size, p, radius)
+        if due:
+            state["o"] = new
+        return due, new
+    o_shifts = run_ring(om, w.scans, orc)
+    assert g_shifts == o_shifts > 20
+    assert gm.origin == state["o"]
+    # the final global map, slab by slab over the loop's extent
+    nonzero = 0
+    for x0 in range(-1280, 1280, 128):
+        lo, hi = (x0, -1280, -64), (x0 + 128, 1280, 64)
+        g = gm.readback(lo, hi)
+        o = om.readback(lo, hi)
+        assert np.array_equal(g[0], o[0]) and np.array_equal(g[1], o[1]), lo
+        nonzero += int((g[1] > 0).sum())
+    say("config3 observed voxels", nonzero)
+    assert nonzero > 1_000_000
+    gm.close()
+    om.close()
+
+
+# -- config 4: uneven scans into 16 maps, through the batch entry point -------
+
+def test_config4_batch_bit_exact():
+    from paper_2310_05766_amd.tsdf import integrate_batch
+    shapes = synth.config4_shapes()
+    say("config4: oracle in worker processes")
+    ref = oracle_runs.config4_oracle(256)
+    scans = [synth.config4_scan(i, shapes[i]) for i in range(256)]
+    spec = synth.MapSpec((256, 256, 256), (-128, -128, -128), 0.08, 5120, 64)
+    maps = [gpu_map(spec.dims, spec.origin, spec.voxel_size, spec.tau_u, spec.w_max) for _ in range(16)]
+    for b0 in range(0, 256, 32):
+        batch = [(maps[s.map_index], s.xyz, s.pose) for s in scans[b0:b0 + 32]]
+        stats = integrate_batch(batch, stats=True)
+        for j, st in enumerate(stats):
+            i = b0 + j
+            assert st == ref[i % 16][2][i // 16], i
+    for k in range(16):
+        g = maps[k].readback(spec.origin, tuple(spec.origin[a] + spec.dims[a] for a in range(3)))
+        assert np.array_equal(g[0], ref[k][0]) and np.array_equal(g[1], ref[k][1]), k
+        maps[k].close()
