@@ -142,6 +142,24 @@ tsdf_status tsdf_store_info(const tsdf_map *m, int64_t *chunks, int64_t *bytes);
 /* Wait until the map's stream has finished all queued work. */
 tsdf_status tsdf_map_synchronize(tsdf_map *m);
 
+/* --- per-kernel timing --------------------------------------------------
+ * While profiling is on, every kernel launch of the map is bracketed by HIP
+ * events recorded on the map's stream. tsdf_profile_enable(m, 1) waits for
+ * the stream and discards earlier records; tsdf_profile_read waits for the
+ * stream and returns the summed duration (ms) and the launch count of one
+ * kernel since profiling was enabled. */
+typedef enum {
+    TSDF_KERNEL_CANDIDATES = 0, /* min-tsdf: walk, distances, packed-key minimum */
+    TSDF_KERNEL_MERGE = 1,      /* averaging: Eq. (1), Eq. (2) */
+    TSDF_KERNEL_PACK = 2,       /* window -> staging (shift, readback) */
+    TSDF_KERNEL_UNPACK = 3,     /* staging -> window (shift) */
+    TSDF_KERNEL_COUNT = 8
+} tsdf_kernel_id;
+
+tsdf_status tsdf_profile_enable(tsdf_map *m, int32_t on);
+tsdf_status tsdf_profile_read(tsdf_map *m, int32_t kernel, double *total_ms, int64_t *launches);
+const char *tsdf_kernel_name(int32_t kernel);
+
 #ifdef __cplusplus
 }
 #endif

@@ -145,15 +145,18 @@ ScratchLayout ScratchLayout::of(int64_t nvox)
     return L;
 }
 
-hipError_t launch_integrate_plain(const ScanParams &P, uint64_t *keys, uint32_t *touched, DevCounters *ctr,
-                                  int16_t *sdf, int16_t *w, int32_t w_max, hipStream_t stream)
+hipError_t launch_candidates(const ScanParams &P, uint64_t *keys, uint32_t *touched, DevCounters *ctr,
+                             hipStream_t stream)
 {
-    if (P.n > 0) {
-        const int64_t blocks = (P.n + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL(k_candidates, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, P, keys, touched, ctr);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+    if (P.n <= 0) return hipSuccess;
+    const int64_t blocks = (P.n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_candidates, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, P, keys, touched, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(uint64_t *keys, const uint32_t *touched, DevCounters *ctr, int16_t *sdf, int16_t *w,
+                        int32_t w_max, hipStream_t stream)
+{
     // 2048 blocks cover the touched list with a grid-stride loop; the list
     // length is only known on the device.
     hipLaunchKernelGGL(k_merge, dim3(2048), dim3(kBlock), 0, stream, keys, touched, ctr, sdf, w, w_max);

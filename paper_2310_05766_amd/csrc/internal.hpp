@@ -52,8 +52,10 @@ struct Chunk {
 };
 
 // Launchers (integrate.hip, shift.hip). All enqueue on `stream`.
-hipError_t launch_integrate_plain(const ScanParams &P, uint64_t *keys, uint32_t *touched, DevCounters *ctr,
-                                  int16_t *sdf, int16_t *w, int32_t w_max, hipStream_t stream);
+hipError_t launch_candidates(const ScanParams &P, uint64_t *keys, uint32_t *touched, DevCounters *ctr,
+                             hipStream_t stream);
+hipError_t launch_merge(uint64_t *keys, const uint32_t *touched, DevCounters *ctr, int16_t *sdf, int16_t *w,
+                        int32_t w_max, hipStream_t stream);
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
 

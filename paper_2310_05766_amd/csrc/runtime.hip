@@ -42,6 +42,10 @@ struct tsdf_map {
     BoxXfer *boxes_dev = nullptr;
     BoxXfer *boxes_host = nullptr;
     int32_t boxes_cap = 0;
+    // per-kernel event timing (off unless enabled)
+    bool prof_on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[TSDF_KERNEL_COUNT];
+    std::vector<hipEvent_t> ev_pool;
     // state
     bool poisoned = false;
     std::atomic<int> busy{0};
@@ -74,6 +78,45 @@ tsdf_status fail_device(tsdf_map *m)
     do {                                                 \
         if ((call) != hipSuccess) return fail_device(m); \
     } while (0)
+
+hipEvent_t take_event(tsdf_map *m)
+{
+    if (!m->ev_pool.empty()) {
+        hipEvent_t e = m->ev_pool.back();
+        m->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Bracket a launch with events on the map's stream when profiling is on.
+hipError_t prof_start(tsdf_map *m, int id)
+{
+    if (!m->prof_on) return hipSuccess;
+    hipEvent_t a = take_event(m), b = take_event(m);
+    if (!a || !b) return hipErrorOutOfMemory;
+    m->prof_ev[id].push_back({a, b});
+    return hipEventRecord(a, m->stream);
+}
+
+hipError_t prof_stop(tsdf_map *m, int id)
+{
+    if (!m->prof_on) return hipSuccess;
+    return hipEventRecord(m->prof_ev[id].back().second, m->stream);
+}
+
+void prof_clear(tsdf_map *m)
+{
+    for (int k = 0; k < TSDF_KERNEL_COUNT; ++k) {
+        for (auto &p : m->prof_ev[k]) {
+            m->ev_pool.push_back(p.first);
+            m->ev_pool.push_back(p.second);
+        }
+        m->prof_ev[k].clear();
+    }
+}
 
 int64_t floor_div64(int64_t a, int64_t b)
 {
@@ -198,6 +241,8 @@ void release(tsdf_map *m)
     if (m->stage_host) (void)hipHostFree(m->stage_host);
     if (m->boxes_dev) (void)hipFree(m->boxes_dev);
     if (m->boxes_host) (void)hipHostFree(m->boxes_host);
+    prof_clear(m);
+    for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
     if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
     delete m;
 }
@@ -317,7 +362,9 @@ tsdf_status stage_out(tsdf_map *m, int32_t nb, int64_t total, int64_t maxv, bool
     int16_t *dsdf = m->stage_dev, *dw = m->stage_dev + m->stage_cap;
     HIPCHK(m, hipMemcpyAsync(m->boxes_dev, m->boxes_host, (size_t)nb * sizeof(BoxXfer), hipMemcpyHostToDevice,
                              m->stream));
+    HIPCHK(m, prof_start(m, TSDF_KERNEL_PACK));
     HIPCHK(m, launch_pack_boxes(m->boxes_dev, nb, maxv, m->sdf, m->w, m->d.dims, dsdf, dw, clear, m->stream));
+    HIPCHK(m, prof_stop(m, TSDF_KERNEL_PACK));
     HIPCHK(m, hipMemcpyAsync(m->stage_host, dsdf, (size_t)total * sizeof(int16_t), hipMemcpyDeviceToHost,
                              m->stream));
     HIPCHK(m, hipMemcpyAsync(m->stage_host + m->stage_cap, dw, (size_t)total * sizeof(int16_t),
@@ -479,7 +526,12 @@ tsdf_status tsdf_integrate_scan(tsdf_map *m, const float *xyz, int64_t n_points,
         m->pinned_cur ^= 1;
         P.xyz = m->dev_pts;
     }
-    HIPCHK(m, launch_integrate_plain(P, m->keys, m->touched, m->ctr, m->sdf, m->w, m->d.w_max, m->stream));
+    HIPCHK(m, prof_start(m, TSDF_KERNEL_CANDIDATES));
+    HIPCHK(m, launch_candidates(P, m->keys, m->touched, m->ctr, m->stream));
+    HIPCHK(m, prof_stop(m, TSDF_KERNEL_CANDIDATES));
+    HIPCHK(m, prof_start(m, TSDF_KERNEL_MERGE));
+    HIPCHK(m, launch_merge(m->keys, m->touched, m->ctr, m->sdf, m->w, m->d.w_max, m->stream));
+    HIPCHK(m, prof_stop(m, TSDF_KERNEL_MERGE));
     if (stats) {
         uint32_t last[4];
         HIPCHK(m, hipMemcpyAsync(last, m->ctr->last, sizeof(last), hipMemcpyDeviceToHost, m->stream));
@@ -570,7 +622,9 @@ tsdf_status tsdf_shift(tsdf_map *m, const int32_t new_origin[3])
                                  m->stream));
         HIPCHK(m, hipMemcpyAsync(dsdf, hs, (size_t)total * sizeof(int16_t), hipMemcpyHostToDevice, m->stream));
         HIPCHK(m, hipMemcpyAsync(dw, hw, (size_t)total * sizeof(int16_t), hipMemcpyHostToDevice, m->stream));
+        HIPCHK(m, prof_start(m, TSDF_KERNEL_UNPACK));
         HIPCHK(m, launch_unpack_boxes(m->boxes_dev, nb, maxv, m->sdf, m->w, m->d.dims, dsdf, dw, m->stream));
+        HIPCHK(m, prof_stop(m, TSDF_KERNEL_UNPACK));
         HIPCHK(m, hipStreamSynchronize(m->stream));
         return TSDF_OK;
     });
@@ -696,6 +750,47 @@ tsdf_status tsdf_store_info(const tsdf_map *m, int64_t *chunks, int64_t *bytes)
     if (chunks) *chunks = (int64_t)m->store.size();
     if (bytes) *bytes = (int64_t)m->store.size() * kChunkVox * 2 * (int64_t)sizeof(int16_t);
     return TSDF_OK;
+}
+
+tsdf_status tsdf_profile_enable(tsdf_map *m, int32_t on)
+{
+    if (!m) return TSDF_EINVAL;
+    Guard g(m);
+    if (!g.ok) return TSDF_EBUSY;
+    if (m->poisoned) return TSDF_EDEVICE;
+    HIPCHK(m, hipStreamSynchronize(m->stream));
+    prof_clear(m);
+    m->prof_on = on != 0;
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_profile_read(tsdf_map *m, int32_t kernel, double *total_ms, int64_t *launches)
+{
+    if (!m || kernel < 0 || kernel >= TSDF_KERNEL_COUNT || !total_ms || !launches) return TSDF_EINVAL;
+    Guard g(m);
+    if (!g.ok) return TSDF_EBUSY;
+    if (m->poisoned) return TSDF_EDEVICE;
+    HIPCHK(m, hipStreamSynchronize(m->stream));
+    double tot = 0.0;
+    for (auto &p : m->prof_ev[kernel]) {
+        float ms = 0.f;
+        HIPCHK(m, hipEventElapsedTime(&ms, p.first, p.second));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)m->prof_ev[kernel].size();
+    return TSDF_OK;
+}
+
+const char *tsdf_kernel_name(int32_t kernel)
+{
+    switch (kernel) {
+    case TSDF_KERNEL_CANDIDATES: return "k_candidates";
+    case TSDF_KERNEL_MERGE: return "k_merge";
+    case TSDF_KERNEL_PACK: return "k_pack";
+    case TSDF_KERNEL_UNPACK: return "k_unpack";
+    default: return "unknown";
+    }
 }
 
 tsdf_status tsdf_map_synchronize(tsdf_map *m)

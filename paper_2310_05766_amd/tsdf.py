@@ -152,6 +152,17 @@ class TsdfMap:
     def synchronize(self):
         check(_abi.lib().tsdf_map_synchronize(self._h), "tsdf_map_synchronize")
 
+    def profile(self, on: bool = True):
+        """Start (clearing earlier records) or stop per-kernel event timing."""
+        check(_abi.lib().tsdf_profile_enable(self._h, int(bool(on))), "tsdf_profile_enable")
+
+    def profile_read(self, kernel: str):
+        """(total_ms, launches) of one kernel since profiling was enabled."""
+        ms, n = C.c_double(), C.c_int64()
+        check(_abi.lib().tsdf_profile_read(self._h, _abi.KERNELS[kernel], C.byref(ms), C.byref(n)),
+              "tsdf_profile_read")
+        return float(ms.value), int(n.value)
+
 
 def integrate_batch(items, stream=None, stats: bool = False):
     """tsdf_integrate_batch over [(TsdfMap, xyz, pose), ...]; scans sharing a
