@@ -95,6 +95,17 @@ def cpu_baseline(workload, max_seconds: float):
     }
 
 
+def _copy_device(torch, dst, src_ptr: int, nbytes: int):
+    """Device-to-device copy from a raw address (the map's weight array)."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    torch.cuda.synchronize()
+    rc = hip.hipMemcpy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src_ptr), nbytes, 3)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -140,6 +151,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-shift", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="warmup + timed steps only (for rocprofv3)")
+    ap.add_argument("--plain-only", action="store_true", help="with --profile-only: per-scan calls only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -150,7 +162,7 @@ def main():
     import torch
 
     import synth
-    from paper_2310_05766_amd.tsdf import TsdfMap
+    from paper_2310_05766_amd.tsdf import TsdfMap, integrate_batch
 
     torch.cuda.set_device(0)
     log("generating config-2 scans")
@@ -159,59 +171,91 @@ def main():
     dev = [torch.from_numpy(s.xyz).to("cuda") for s in w.scans]
     poses = [s.pose for s in w.scans]
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
+    # a stream of our own (default priority): the map, its batches and the
+    # timing events all live on it
+    stream = torch.cuda.Stream()
     gm = TsdfMap.from_spec(spec, stream=stream)
 
-    # per-scan counts (state independent): U, visits, valid points
+    # per-scan counts (state independent): U, visits, valid points; on the
+    # fresh map, the voxels any scan touches (the union) are those with w > 0
     stats = [gm.integrate(x, p, stats=True) for x, p in zip(dev, poses)]
     U_step = sum(s["voxels_updated"] for s in stats)
     N_step = sum(s["points_in"] for s in stats)
     visits_step = sum(s["visits"] for s in stats)
+    _sdf_ptr, w_ptr, _st = gm.device_arrays()
+    w_view = torch.empty(spec.n_voxels, dtype=torch.int16, device="cuda")
+    _copy_device(torch, w_view, w_ptr, spec.n_voxels * 2)
+    U_union = int((w_view > 0).sum().item())
+    del w_view
+    n_scans = len(dev)
 
-    def step():
+    batch_items = [(gm, x, p) for x, p in zip(dev, poses)]
+
+    def step_plain():
         for x, p in zip(dev, poses):
             gm.integrate(x, p)
 
-    log("warmup")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log("timed steps")
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    def step_batched():
+        integrate_batch(batch_items, stream=stream)
+
+    def timed(step):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    log("plain per-scan steps")
+    dt_plain = timed(step_plain)
+    if args.profile_only and args.plain_only:
+        log(f"profile-only: plain {dt_plain * 1e3 / args.steps:.3f} ms/step")
+        gm.close()
+        return
+    log("batched steps")
+    dt = timed(step_batched)
     if args.profile_only:
-        log(f"profile-only: {dt * 1e3 / args.steps:.3f} ms/step")
+        log(f"profile-only: plain {dt_plain * 1e3 / args.steps:.3f} ms/step, batched {dt * 1e3 / args.steps:.3f} ms/step")
         gm.close()
         return
 
-    # per-kernel durations from HIP events on the map's stream
-    log("kernel timing")
-    gm.profile(True)
-    for _ in range(max(3, args.steps // 2)):
-        step()
-    kt = {}
-    for k in ("k_candidates", "k_merge"):
-        ms, n = gm.profile_read(k)
-        if n:
-            kt[k] = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / n}
-    gm.profile(False)
-    dominant = max(kt, key=lambda k: kt[k]["total_ms"])
-    n_scans = len(dev)
-    # algorithmic bytes (12 per point incl. no-return slots, 128 per pose,
-    # 8 per voxel update: int16 sdf + int16 w read once and written once)
-    alg = {
-        "k_candidates": (12.0 * N_step + 128.0 * n_scans) / n_scans,
-        "k_merge": 8.0 * U_step / n_scans,
-    }
-    achieved = alg[dominant] / (kt[dominant]["avg_us"] * 1e-6) / 1e9
-    traffic = read_traffic(dominant, "config2")
-    scan_kernel_us = sum(v["avg_us"] for v in kt.values())
-    B_scan = (12.0 * N_step + 128.0 * n_scans + 8.0 * U_step) / n_scans
+    def stage_times(step, reps):
+        gm.profile(True)
+        for _ in range(reps):
+            step()
+        out = {}
+        for k in ("k_bin", "k_tile"):
+            ms, n = gm.profile_read(k)
+            if n:
+                out[k] = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / n}
+        gm.profile(False)
+        return out
 
-    # synchronous per-scan latency
+    log("kernel timing")
+    kt_plain = stage_times(step_plain, max(3, args.steps // 4))
+    # batched launches go through the stream's batch engine: time them with
+    # torch events on the same stream (the map's stream is that stream)
+    kt = {}
+    reps = max(3, args.steps // 2)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        step_batched()
+        b.record(stream)
+    torch.cuda.synchronize()
+    launch_ms = [a.elapsed_time(b) for a, b in ev]
+    kt["batch"] = {"total_ms": sum(launch_ms), "launches": reps, "avg_us": 1e3 * sum(launch_ms) / reps}
+
+    # algorithmic bytes: 12 per point (no-return slots included), 128 per
+    # pose, 8 per voxel update (int16 sdf + int16 w read once, written once)
+    B_scans = 12.0 * N_step + 128.0 * n_scans + 8.0 * U_step           # scan by scan
+    B_batch = 12.0 * N_step + 128.0 * n_scans + 8.0 * U_union          # one pass over the batch
+    achieved = B_batch / (kt["batch"]["avg_us"] * 1e-6) / 1e9
+    traffic = read_traffic("batch", "config2")
+
+    # synchronous per-scan latency (plain path)
     log("latency")
     lat = []
     for _ in range(3):
@@ -245,33 +289,35 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{n_scans} OS1-128-shaped scans (128x1024, seeded outdoor scene, FP64 poses) -> "
-                        "fixed 512x512x256 map at 6.4 cm, tau 5 voxels, w_max 64; one step = the whole sequence",
+                        "fixed 512x512x256 map at 6.4 cm, tau 5 voxels, w_max 64; one step = the whole sequence, "
+                        "integrated as one ordered batch",
             "scans_per_step": n_scans,
             "points_per_step": N_step,
             "voxel_updates_per_step": U_step,
+            "distinct_voxels_per_step": U_union,
             "visits_per_step": visits_step,
             "storage": "int16 sdf + int16 weight per voxel",
         },
         "scans_per_s": n_scans * args.steps / dt,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "max": float(lat_ms.max()), "mode": "synchronous per-scan call"},
+        "plain": {
+            "value": U_step * args.steps / dt_plain,
+            "scans_per_s": n_scans * args.steps / dt_plain,
+            "ms_per_step": dt_plain * 1e3 / args.steps,
+            "kernels": kt_plain,
+        },
         "kernels": kt,
         "roofline": {
             "bound": "hbm",
-            "kernel": dominant,
+            "kernel": "batch (k_bin + k_alloc + k_tile on one stream)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "algorithmic_bytes_per_launch": alg[dominant],
-        },
-        "scan_roofline": {
-            "algorithmic_bytes_per_scan": B_scan,
-            "kernel_us_per_scan": scan_kernel_us,
-            "achieved_GBps": B_scan / (scan_kernel_us * 1e-6) / 1e9,
-            "wall_us_per_scan": dt * 1e6 / (args.steps * n_scans),
-            "wall_GBps": B_scan * n_scans * args.steps / dt / 1e9,
+            "algorithmic_bytes_per_launch": B_batch,
+            "algorithmic_bytes_scan_by_scan": B_scans,
         },
         "shift": shift,
         "cpu_baseline": cpu,

@@ -46,7 +46,8 @@ typedef enum { TSDF_PTR_HOST = 0, TSDF_PTR_DEVICE = 1 } tsdf_ptr_kind;
 
 typedef struct {
     int32_t dims[3];     /* window size in voxels, each >= 1; nx*ny*nz < 2^31 */
-    int32_t origin[3];   /* global voxel index of the window's min corner */
+    int32_t origin[3];   /* global voxel index of the window's min corner; the
+                            window must lie within [-2^20, 2^20) voxels */
     double voxel_size_m; /* > 0 */
     int32_t tau_q10;     /* truncation tau in 1/1024-voxel units, 1..32767 */
     int32_t w_max;       /* weight cap of Eq. (2), 1..32767 */
@@ -116,6 +117,14 @@ typedef struct {
 tsdf_status tsdf_integrate_batch(const tsdf_scan_desc *scans, int32_t count, tsdf_ptr_kind kind,
                                  void *hip_stream, tsdf_scan_stats *stats /* count entries, nullable */);
 
+/* A batch runs on hip_stream (NULL: the first scan's map's stream), ordered
+ * after earlier work on every map it touches, and later work on those maps
+ * is ordered after it. The library keeps a batch engine (device tables,
+ * staging) per stream; tsdf_batch_release frees the one of a stream after
+ * waiting for it, and must be called before the caller destroys a stream it
+ * passed here. (Destroying a map drops the engine of the map's own stream.) */
+tsdf_status tsdf_batch_release(void *hip_stream);
+
 /* --- inspection and helpers (no method arithmetic beyond what is named) --- */
 
 const char *tsdf_status_string(tsdf_status s);
@@ -149,14 +158,22 @@ tsdf_status tsdf_map_synchronize(tsdf_map *m);
  * stream and returns the summed duration (ms) and the launch count of one
  * kernel since profiling was enabled. */
 typedef enum {
-    TSDF_KERNEL_CANDIDATES = 0, /* min-tsdf: walk, distances, packed-key minimum */
-    TSDF_KERNEL_MERGE = 1,      /* averaging: Eq. (1), Eq. (2) */
+    TSDF_KERNEL_BIN = 0,        /* ray binning by window tile (count, prefix, fill) */
+    TSDF_KERNEL_TILE = 1,       /* per tile: walk, distances, LDS minimum, Eq. (1), Eq. (2) */
     TSDF_KERNEL_PACK = 2,       /* window -> staging (shift, readback) */
     TSDF_KERNEL_UNPACK = 3,     /* staging -> window (shift) */
     TSDF_KERNEL_COUNT = 8
 } tsdf_kernel_id;
 
 tsdf_status tsdf_profile_enable(tsdf_map *m, int32_t on);
+
+/* Candidate-buffer tiling of the integration: the window is cut into tiles
+ * of 2^log2_tile[a] voxels per axis (each in [2, 6], z at least 3,
+ * 2^9..2^13 voxels per tile; a tile's candidate keys live in 8 bytes of LDS per voxel), handled
+ * by tile_workgroups persistent workgroups (0: as many as fit the device).
+ * The arithmetic, and so every result, is the same for every tiling. */
+tsdf_status tsdf_map_set_tiling(tsdf_map *m, const int32_t log2_tile[3], int32_t tile_workgroups);
+tsdf_status tsdf_map_get_tiling(const tsdf_map *m, int32_t log2_tile[3], int32_t *tile_workgroups);
 tsdf_status tsdf_profile_read(tsdf_map *m, int32_t kernel, double *total_ms, int64_t *launches);
 const char *tsdf_kernel_name(int32_t kernel);
 

@@ -19,9 +19,10 @@ EXPORTS = (
     "tsdf_scratch_bytes", "tsdf_map_create", "tsdf_map_create_in", "tsdf_map_destroy", "tsdf_integrate_scan",
     "tsdf_shift", "tsdf_readback", "tsdf_integrate_batch", "tsdf_status_string", "tsdf_map_origin",
     "tsdf_map_device_arrays", "tsdf_recentre_origin", "tsdf_store_info", "tsdf_map_synchronize",
-    "tsdf_profile_enable", "tsdf_profile_read", "tsdf_kernel_name",
+    "tsdf_profile_enable", "tsdf_profile_read", "tsdf_kernel_name", "tsdf_map_set_tiling",
+    "tsdf_map_get_tiling", "tsdf_batch_release",
 )
-KERNELS = {"k_candidates": 0, "k_merge": 1, "k_pack": 2, "k_unpack": 3}
+KERNELS = {"k_bin": 0, "k_tile": 1, "k_pack": 2, "k_unpack": 3}
 
 
 class MapDesc(C.Structure):
@@ -92,6 +93,12 @@ def lib():
     L.tsdf_profile_enable.argtypes = [vp, C.c_int32]
     L.tsdf_profile_read.restype = st
     L.tsdf_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.tsdf_map_set_tiling.restype = st
+    L.tsdf_map_set_tiling.argtypes = [vp, i32p, C.c_int32]
+    L.tsdf_map_get_tiling.restype = st
+    L.tsdf_map_get_tiling.argtypes = [vp, i32p, C.POINTER(C.c_int32)]
+    L.tsdf_batch_release.restype = st
+    L.tsdf_batch_release.argtypes = [vp]
     L.tsdf_kernel_name.restype = C.c_char_p
     L.tsdf_kernel_name.argtypes = [C.c_int32]
     _lib = L

@@ -1,0 +1,564 @@
+// Batched integration (FeatSense, arXiv 2310.05766, Sec. VI): any number of
+// registered scans, into any number of maps, in one pass of five kernels.
+//
+// Each map window is cut into tiles of 2^lt voxels per axis (window-relative
+// coordinates). The per-scan volume V of the min-tsdf step never reaches HBM:
+// a workgroup owns one tile, keeps its candidate keys (|s|, point index, s)
+// in LDS and resolves them with ds_min_u64 (order independent, one winner per
+// voxel), then applies the averaging step, Eq. (1) and Eq. (2), to the tile.
+// When several scans of one map share a batch, the tile's SDF and weights
+// stay in LDS while its workgroup applies those scans one after another, in
+// submission order, and go back to HBM once.
+//
+//   k_bin<count>  every ray walks its band on the grid of tiles (the exact
+//                 walk with tile-sized cells) and counts one entry per tile;
+//                 keys are (sequence slot, tile), merged per block in an LDS
+//                 table so that each block sends one atomic per distinct key
+//   k_alloc       a run of the entry buffer per (sequence slot, tile), runs of
+//                 one tile consecutive in sequence order; list of busy tiles
+//   k_bin<fill>   the same walk, writing point indices into the runs
+//   k_tile        per busy tile, per sequence slot in order: every ray jumps
+//                 to its first voxel in the tile (exact crossing counts) and
+//                 walks the tile; candidates meet in LDS; then the merge
+//   k_stats       per-scan counts, when asked for
+#include "internal.hpp"
+
+namespace tsdf {
+
+namespace {
+
+constexpr int kTileBlock = 256;
+constexpr int kAllocBlock = 1024;
+
+__device__ __forceinline__ uint32_t lane() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t key)
+{
+    return (key * 2654435761u) >> (32 - 10);  // kHashSlots = 2^10
+}
+
+template <bool kFill>
+__global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
+{
+    __shared__ uint32_t h_key[kHashSlots];  // key + 1; 0 = free
+    __shared__ uint32_t h_cnt[kHashSlots];
+    __shared__ uint32_t h_base[kFill ? kHashSlots : 1];
+    __shared__ uint16_t s_slot[kFill ? kMaxEmit * kBinBlock : 1];
+    __shared__ uint16_t s_rank[kFill ? kMaxEmit * kBinBlock : 1];
+    __shared__ uint32_t s_valid;
+    const BatchHdr H = *B.hdr;
+    if (!kFill && blockIdx.x == 0 && threadIdx.x == 0) {
+        // the allocation counters of the previous batch are done with (the
+        // grid always has a block 0, also for a batch without points)
+        B.ctl->n_nonempty = 0;
+        B.ctl->entries = 0;
+        B.ctl->overflow = 0;
+        for (int q = 0; q < kQueues; ++q) B.ctl->work[q] = 0;
+    }
+    if (blockIdx.x >= H.nblocks) return;
+    for (uint32_t j = threadIdx.x; j < kHashSlots; j += kBinBlock) {
+        h_key[j] = 0;
+        h_cnt[j] = 0;
+    }
+    if (threadIdx.x == 0) s_valid = 0;
+    __syncthreads();
+
+    const uint32_t s = B.block_scan[blockIdx.x];
+    const ScanDev &SD = B.scans[s];
+    const MapDev &MD = B.maps[SD.map];
+    const int64_t i = (int64_t)(blockIdx.x - SD.block0) * kBinBlock + threadIdx.x;
+    const RayParams rp = SD.rp;
+    Ray R;
+    Walk W;
+    bool active = false;
+    int32_t q[3] = {0, 0, 0};
+    if (i < SD.n) {
+        const float *p = SD.xyz + 3 * i;
+        if (quantise(p[0], p[1], p[2], rp, q) && make_ray(q, rp, R)) {
+            active = true;
+            // the tiles of the band's voxels are the cells of the same exact
+            // walk on the grid of tiles (floor of a floor division)
+            const int32_t lc[3] = {10 + H.lt[0], 10 + H.lt[1], 10 + H.lt[2]};
+            const int32_t base[3] = {1024 * MD.origin[0], 1024 * MD.origin[1], 1024 * MD.origin[2]};
+            walk_init_cells(R, W, lc, base);
+        }
+    }
+    const uint32_t valid = active ? 1u : 0u;
+    const uint32_t key0 = (uint32_t)SD.seq * H.gtiles + MD.tile_base;
+    int ne = 0;
+    while (active) {
+        if ((uint32_t)W.g[0] < (uint32_t)MD.nt[0] && (uint32_t)W.g[1] < (uint32_t)MD.nt[1] &&
+            (uint32_t)W.g[2] < (uint32_t)MD.nt[2]) {
+            const uint32_t key =
+                key0 + ((uint32_t)W.g[0] * (uint32_t)MD.nt[1] + (uint32_t)W.g[1]) * (uint32_t)MD.nt[2] + (uint32_t)W.g[2];
+            uint32_t h = hash_slot(key), slot = 0xffffu;
+            for (int probe = 0; probe < kHashSlots; ++probe) {
+                const uint32_t old = atomicCAS(&h_key[h], 0u, key + 1u);
+                if (old == 0u || old == key + 1u) {
+                    slot = h;
+                    break;
+                }
+                h = (h + 1u) & (kHashSlots - 1u);
+            }
+            if (slot != 0xffffu && (!kFill || ne < kMaxEmit)) {
+                const uint32_t rank = atomicAdd(&h_cnt[slot], 1u);
+                if (kFill) {
+                    s_slot[ne * kBinBlock + threadIdx.x] = (uint16_t)slot;
+                    s_rank[ne * kBinBlock + threadIdx.x] = (uint16_t)rank;
+                }
+            } else if (kFill) {  // table full or very long band: straight to the tile's run
+                const uint32_t pos = atomicAdd(&B.cursor[key], 1u);
+                if (pos < H.cap) B.entries[pos] = make_uint4((uint32_t)i, (uint32_t)q[0], (uint32_t)q[1], (uint32_t)q[2]);
+                else atomicOr(&B.ctl->overflow, 1u);
+            } else {
+                atomicAdd(&B.counts[key], 1u);
+            }
+            ++ne;
+        }
+        active = walk_next(W);
+    }
+    if (!kFill && valid) atomicAdd(&s_valid, 1u);
+    __syncthreads();
+    // one global atomic per distinct key of this block
+    for (uint32_t j = threadIdx.x; j < kHashSlots; j += kBinBlock) {
+        const uint32_t k1 = h_key[j];
+        const uint32_t c = h_cnt[j];
+        if (k1 == 0u || c == 0u) continue;
+        if (kFill) h_base[j] = atomicAdd(&B.cursor[k1 - 1u], c);
+        else atomicAdd(&B.counts[k1 - 1u], c);
+    }
+    if (!kFill) {
+        if (threadIdx.x == 0) B.valid_part[blockIdx.x] = s_valid;
+        return;
+    }
+    __syncthreads();
+    // each record carries the point's fixed-point position, so the tile pass
+    // needs neither the point nor the pose again
+    const uint4 rec = make_uint4((uint32_t)i, (uint32_t)q[0], (uint32_t)q[1], (uint32_t)q[2]);
+    const int nl = ne < kMaxEmit ? ne : kMaxEmit;
+    for (int k = 0; k < nl; ++k) {
+        const uint32_t pos = h_base[s_slot[k * kBinBlock + threadIdx.x]] + s_rank[k * kBinBlock + threadIdx.x];
+        if (pos < H.cap) B.entries[pos] = rec;
+        else atomicOr(&B.ctl->overflow, 1u);
+    }
+}
+
+// Map slot of a global tile: the last map whose first tile is <= g.
+__device__ __forceinline__ int32_t map_of_tile(const BatchArrays &B, int32_t nmaps, uint32_t g)
+{
+    int32_t lo = 0, hi = nmaps - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (B.maps[mid].tile_base <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Runs of the entry buffer: one per (sequence slot, tile), a tile's runs
+// consecutive in sequence order; the tile is listed as busy. Runs may lie in
+// any order, so they are handed out by atomic allocation, one atomic per
+// block and counter (same-address device atomics serialise; a block prefix
+// keeps them few).
+__global__ __launch_bounds__(kAllocBlock) void k_alloc(BatchArrays B)
+{
+    __shared__ uint32_t s_wc[kAllocBlock / 64], s_wn[kAllocBlock / 64];
+    __shared__ uint32_t s_base_c, s_base_n;
+    const BatchHdr H = *B.hdr;
+    const uint32_t t = blockIdx.x * kAllocBlock + threadIdx.x;
+    if (blockIdx.x * kAllocBlock >= H.gtiles) return;
+    const uint32_t wave = threadIdx.x / 64;
+    uint32_t c = 0;
+    if (t < H.gtiles)
+        for (int sq = 0; sq < H.S; ++sq) c += B.counts[(uint32_t)sq * H.gtiles + t];
+    uint32_t pc = c, pn = c != 0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t a = (uint32_t)__shfl_up((int)pc, off);
+        const uint32_t b = (uint32_t)__shfl_up((int)pn, off);
+        if (lane() >= (uint32_t)off) {
+            pc += a;
+            pn += b;
+        }
+    }
+    if (lane() == 63) {
+        s_wc[wave] = pc;
+        s_wn[wave] = pn;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t sc = 0, sn = 0;
+        for (int k = 0; k < kAllocBlock / 64; ++k) {
+            const uint32_t a = s_wc[k], b = s_wn[k];
+            s_wc[k] = sc;
+            s_wn[k] = sn;
+            sc += a;
+            sn += b;
+        }
+        s_base_c = sc ? atomicAdd(&B.ctl->entries, sc) : 0u;
+        s_base_n = sn ? atomicAdd(&B.ctl->n_nonempty, sn) : 0u;
+    }
+    __syncthreads();
+    if (c) {
+        uint32_t off = s_base_c + s_wc[wave] + pc - c;
+        for (int sq = 0; sq < H.S; ++sq) {
+            const uint32_t k = (uint32_t)sq * H.gtiles + t;
+            const uint32_t ck = B.counts[k];
+            B.offsets[k] = off;
+            B.cursor[k] = off;
+            off += ck;
+        }
+        B.nonempty[s_base_n + s_wn[wave] + pn - 1] = t;
+        B.nonempty_map[s_base_n + s_wn[wave] + pn - 1] = (uint32_t)map_of_tile(B, H.nmaps, t);
+    }
+}
+
+__device__ __forceinline__ int32_t rdiv_small(int32_t n, int32_t d)
+{
+    const uint32_t a = (uint32_t)(n < 0 ? -n : n);
+    const uint32_t k = (2u * a + (uint32_t)d) / (2u * (uint32_t)d);
+    return n < 0 ? -(int32_t)k : (int32_t)k;
+}
+
+// Eq. (1) with one unit of weight, Eq. (2).
+__device__ __forceinline__ void merge_one(int16_t &sdf, int16_t &w, uint64_t key, int32_t w_max)
+{
+    const int32_t v = (int16_t)(uint16_t)(key & 0xffffu);
+    const int32_t gw = w, gv = sdf;
+    sdf = (int16_t)rdiv_small(gv * gw + v, gw + 1);
+    w = (int16_t)(gw + 1 < w_max ? gw + 1 : w_max);
+}
+
+constexpr int kMaxGroup = 8;
+
+// Merge the touched voxels of one run of 8 z-consecutive voxels straight
+// into HBM (one busy sequence slot on the tile).
+__device__ __forceinline__ uint32_t merge_run_direct(uint64_t *kr, const MapDev &MD, int64_t row, int32_t rz0)
+{
+    uint64_t kk[8];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        kk[j] = kr[j];
+        any |= kk[j] != kEmptyKey;
+    }
+    if (!any) return 0;
+    uint32_t updated = 0;
+    if (MD.vec_ok) {
+        // 8 int16 of sdf and of w in one 16-byte access each
+        int32_t sz = rz0 + MD.ring0[2];
+        sz -= sz >= MD.dims[2] ? MD.dims[2] : 0;
+        int4 sv = *reinterpret_cast<const int4 *>(MD.sdf + row + sz);
+        int4 wv = *reinterpret_cast<const int4 *>(MD.w + row + sz);
+        int16_t *sp = reinterpret_cast<int16_t *>(&sv);
+        int16_t *wp = reinterpret_cast<int16_t *>(&wv);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (kk[j] != kEmptyKey) {
+                merge_one(sp[j], wp[j], kk[j], MD.w_max);
+                kr[j] = kEmptyKey;
+                ++updated;
+            }
+        *reinterpret_cast<int4 *>(MD.sdf + row + sz) = sv;
+        *reinterpret_cast<int4 *>(MD.w + row + sz) = wv;
+    } else {
+        for (int j = 0; j < 8; ++j) {
+            if (kk[j] == kEmptyKey) continue;
+            int32_t sz = rz0 + j + MD.ring0[2];
+            sz -= sz >= MD.dims[2] ? MD.dims[2] : 0;
+            merge_one(MD.sdf[row + sz], MD.w[row + sz], kk[j], MD.w_max);
+            kr[j] = kEmptyKey;
+            ++updated;
+        }
+    }
+    return updated;
+}
+
+// Slot of window-relative voxel r of a map.
+__device__ __forceinline__ int64_t slot_of_rel(const MapDev &MD, int32_t rx, int32_t ry, int32_t rz)
+{
+    int32_t sx = rx + MD.ring0[0], sy = ry + MD.ring0[1], sz = rz + MD.ring0[2];
+    sx -= sx >= MD.dims[0] ? MD.dims[0] : 0;
+    sy -= sy >= MD.dims[1] ? MD.dims[1] : 0;
+    sz -= sz >= MD.dims[2] ? MD.dims[2] : 0;
+    return ((int64_t)sx * MD.dims[1] + sy) * MD.dims[2] + sz;
+}
+
+// Persistent tile pass. Workgroup b first takes busy tile b, then pulls
+// further tiles from queue b % 8 (one queue per XCD keeps same-address
+// atomics spread). Per tile, the busy sequence slots are taken in groups of
+// G: the candidates of a group's runs are computed together, one LDS key
+// buffer per slot, then each voxel applies the group's scans in submission
+// order. A tile busy in several slots keeps its SDF and weights in LDS.
+__global__ __launch_bounds__(kTileBlock) void k_tile(BatchArrays B)
+{
+    extern __shared__ uint64_t s_keys[];  // G * tvox keys, then the cached tile: tvox sdf, tvox w
+    __shared__ uint32_t s_beg[kMaxSeq], s_cnt[kMaxSeq];
+    __shared__ int32_t s_scan[kMaxSeq];
+    __shared__ int32_t s_o[kMaxGroup][3], s_tau[kMaxGroup];
+    __shared__ uint32_t s_vis[kMaxGroup], s_upd[kMaxGroup];
+    __shared__ uint32_t s_busy, s_job;
+    const BatchHdr H = *B.hdr;
+    const int32_t lsum = H.lt[0] + H.lt[1] + H.lt[2];
+    const uint32_t tvox = 1u << lsum;
+    const int32_t G = H.G;
+    int16_t *c_sdf = reinterpret_cast<int16_t *>(s_keys + (size_t)G * tvox);
+    int16_t *c_w = c_sdf + tvox;
+    const uint32_t nne = B.ctl->n_nonempty;
+    const uint32_t ez = 1u << H.lt[2], ey = 1u << H.lt[1];
+    uint32_t job = blockIdx.x;
+    if (job >= nne) return;
+    const uint32_t queue = blockIdx.x % kQueues;
+    for (uint32_t v = threadIdx.x; v < (uint32_t)G * tvox; v += kTileBlock) s_keys[v] = kEmptyKey;
+    while (job < nne) {
+        const uint32_t g = B.nonempty[job];
+        const int32_t mb = (int32_t)B.nonempty_map[job];
+        // the tile's runs, one load per sequence slot, all in flight together
+        if (threadIdx.x < (uint32_t)H.S) {
+            const uint32_t k = threadIdx.x * H.gtiles + g;
+            const uint32_t c = B.counts[k];
+            s_cnt[threadIdx.x] = c;
+            s_beg[threadIdx.x] = c ? B.offsets[k] : 0u;
+            s_scan[threadIdx.x] = c ? B.seq_scan[mb * H.S + threadIdx.x] : -1;
+        }
+        if (threadIdx.x == 0) s_busy = 0;
+        __syncthreads();
+        if (threadIdx.x < (uint32_t)H.S && s_cnt[threadIdx.x]) atomicAdd(&s_busy, 1u);
+        const MapDev &MD = B.maps[mb];
+        const uint32_t t = g - MD.tile_base;
+        const uint32_t tz = t % (uint32_t)MD.nt[2];
+        const uint32_t txy = t / (uint32_t)MD.nt[2];
+        const int32_t t0[3] = {(int32_t)(txy / (uint32_t)MD.nt[1]) << H.lt[0],
+                               (int32_t)(txy % (uint32_t)MD.nt[1]) << H.lt[1], (int32_t)tz << H.lt[2]};
+        // the tile's voxel box, clipped to the window, in global coordinates
+        int32_t blo[3], bhi[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            blo[a] = MD.origin[a] + t0[a];
+            bhi[a] = MD.origin[a] + min(t0[a] + (1 << H.lt[a]), MD.dims[a]);
+        }
+        __syncthreads();
+        const bool cached = s_busy > 1;
+        if (cached) {
+            for (uint32_t v = threadIdx.x; v < tvox; v += kTileBlock) {
+                const int32_t rz = (int32_t)(v & (ez - 1)) + t0[2];
+                const int32_t ry = (int32_t)((v >> H.lt[2]) & (ey - 1)) + t0[1];
+                const int32_t rx = (int32_t)(v >> (H.lt[1] + H.lt[2])) + t0[0];
+                if (rx >= MD.dims[0] || ry >= MD.dims[1] || rz >= MD.dims[2]) continue;
+                const int64_t slot = slot_of_rel(MD, rx, ry, rz);
+                c_sdf[v] = MD.sdf[slot];
+                c_w[v] = MD.w[slot];
+            }
+        }
+        for (int sq0 = 0; sq0 < H.S; sq0 += G) {
+            const int ng = min(G, H.S - sq0);
+            uint32_t gsum = 0;
+            for (int r = 0; r < ng; ++r) gsum += s_cnt[sq0 + r];
+            if (gsum == 0u) continue;  // same value for the whole workgroup
+            if (threadIdx.x < (uint32_t)ng) {
+                const int r = (int)threadIdx.x;
+                s_vis[r] = 0;
+                s_upd[r] = 0;
+                if (s_cnt[sq0 + r]) {
+                    const ScanDev &SD = B.scans[s_scan[sq0 + r]];
+                    s_o[r][0] = SD.rp.o[0];
+                    s_o[r][1] = SD.rp.o[1];
+                    s_o[r][2] = SD.rp.o[2];
+                    s_tau[r] = SD.rp.tau;
+                }
+            }
+            __syncthreads();
+            for (uint32_t e = threadIdx.x; e < gsum; e += kTileBlock) {
+                // which run of the group entry e belongs to
+                int r = 0;
+                uint32_t ee = e;
+                while (ee >= s_cnt[sq0 + r]) {
+                    ee -= s_cnt[sq0 + r];
+                    ++r;
+                }
+                const uint32_t beg = s_beg[sq0 + r];
+                // the run lies inside the entry buffer unless the fill overflowed
+                if (beg + ee >= H.cap) continue;
+                const uint4 rec = B.entries[beg + ee];
+                const uint32_t i = rec.x;
+                const int32_t q[3] = {(int32_t)rec.y, (int32_t)rec.z, (int32_t)rec.w};
+                RayParams rp;
+                rp.o[0] = s_o[r][0];
+                rp.o[1] = s_o[r][1];
+                rp.o[2] = s_o[r][2];
+                rp.tau = s_tau[r];
+                Ray R;
+                Walk W;
+                // every binned point has a ray (it was kept when binned)
+                make_ray(q, rp, R);
+                walk_init(R, W);
+                if (!walk_enter_box(W, blo, bhi)) continue;
+                uint64_t *kb = s_keys + (size_t)r * tvox;
+                uint32_t visits = 0;
+                // the voxels of the walk inside the box are one run
+                do {
+                    if (W.g[0] >= bhi[0] || W.g[1] >= bhi[1] || W.g[2] >= bhi[2] || W.g[0] < blo[0] ||
+                        W.g[1] < blo[1] || W.g[2] < blo[2])
+                        break;
+                    const uint32_t r0 = (uint32_t)(W.g[0] - blo[0]), r1 = (uint32_t)(W.g[1] - blo[1]),
+                                   r2 = (uint32_t)(W.g[2] - blo[2]);
+                    const int32_t sd = voxel_sdf(W.n, R, rp.tau);
+                    const uint32_t lv = (((r0 << H.lt[1]) + r1) << H.lt[2]) + r2;
+                    atomicMin((unsigned long long *)&kb[lv], (unsigned long long)pack_key(sd, i));
+                    ++visits;
+                } while (walk_next(W));
+                if (H.want_stats && visits) atomicAdd(&s_vis[r], visits);
+            }
+            __syncthreads();
+            if (cached) {
+                // each voxel applies the group's scans in submission order
+                uint32_t upd[kMaxGroup];
+#pragma unroll
+                for (int r = 0; r < kMaxGroup; ++r) upd[r] = 0;
+                for (uint32_t v = threadIdx.x; v < tvox; v += kTileBlock) {
+                    for (int r = 0; r < ng; ++r) {
+                        uint64_t *kp = &s_keys[(size_t)r * tvox + v];
+                        const uint64_t key = *kp;
+                        if (key == kEmptyKey) continue;
+                        merge_one(c_sdf[v], c_w[v], key, MD.w_max);
+                        *kp = kEmptyKey;
+                        if (H.want_stats) {
+#pragma unroll
+                            for (int rr = 0; rr < kMaxGroup; ++rr) upd[rr] += rr == r;
+                        }
+                    }
+                }
+                if (H.want_stats)
+                    for (int r = 0; r < ng; ++r)
+                        if (upd[r]) atomicAdd(&s_upd[r], upd[r]);
+            } else {
+                // a single busy slot: merge straight into HBM, runs of 8
+                int rb = 0;
+                while (s_cnt[sq0 + rb] == 0u) ++rb;
+                uint32_t updated = 0;
+                for (uint32_t v0 = threadIdx.x * 8u; v0 < tvox; v0 += kTileBlock * 8u) {
+                    const int32_t rz0 = (int32_t)(v0 & (ez - 1)) + t0[2];
+                    const int32_t ry = (int32_t)((v0 >> H.lt[2]) & (ey - 1)) + t0[1];
+                    const int32_t rx = (int32_t)(v0 >> (H.lt[1] + H.lt[2])) + t0[0];
+                    if (rx >= MD.dims[0] || ry >= MD.dims[1] || rz0 >= MD.dims[2]) continue;  // no key there
+                    int32_t sx = rx + MD.ring0[0], sy = ry + MD.ring0[1];
+                    sx -= sx >= MD.dims[0] ? MD.dims[0] : 0;
+                    sy -= sy >= MD.dims[1] ? MD.dims[1] : 0;
+                    const int64_t row = ((int64_t)sx * MD.dims[1] + sy) * MD.dims[2];
+                    updated += merge_run_direct(&s_keys[(size_t)rb * tvox + v0], MD, row, rz0);
+                }
+                if (H.want_stats && updated) atomicAdd(&s_upd[rb], updated);
+            }
+            __syncthreads();
+            if (threadIdx.x < (uint32_t)ng && s_cnt[sq0 + threadIdx.x]) {
+                const uint32_t k = (uint32_t)(sq0 + threadIdx.x) * H.gtiles + g;
+                B.counts[k] = 0;  // ready for the next batch
+                if (H.want_stats) {
+                    B.tile_vis[k] = s_vis[threadIdx.x];
+                    B.tile_upd[k] = s_upd[threadIdx.x];
+                }
+            }
+        }
+        if (cached) {
+            for (uint32_t v = threadIdx.x; v < tvox; v += kTileBlock) {
+                const int32_t rz = (int32_t)(v & (ez - 1)) + t0[2];
+                const int32_t ry = (int32_t)((v >> H.lt[2]) & (ey - 1)) + t0[1];
+                const int32_t rx = (int32_t)(v >> (H.lt[1] + H.lt[2])) + t0[0];
+                if (rx >= MD.dims[0] || ry >= MD.dims[1] || rz >= MD.dims[2]) continue;
+                const int64_t slot = slot_of_rel(MD, rx, ry, rz);
+                MD.sdf[slot] = c_sdf[v];
+                MD.w[slot] = c_w[v];
+            }
+        }
+        // next tile from this workgroup's queue
+        if (threadIdx.x == 0) s_job = gridDim.x + queue + kQueues * atomicAdd(&B.ctl->work[queue], 1u);
+        __syncthreads();
+        job = s_job;
+    }
+}
+
+// Per-scan counts (one workgroup per scan): voxels updated and visits over
+// the scan's (sequence slot, tile) records, which it clears again, and
+// points with a ray over the scan's binning blocks.
+__global__ __launch_bounds__(256) void k_stats(BatchArrays B)
+{
+    __shared__ uint32_t s_sum[3][256];
+    const BatchHdr H = *B.hdr;
+    const uint32_t s = blockIdx.x;
+    if (!H.want_stats || s >= (uint32_t)H.nscans) return;
+    const ScanDev &SD = B.scans[s];
+    const MapDev &MD = B.maps[SD.map];
+    uint32_t vis = 0, upd = 0, val = 0;
+    const uint32_t k0 = (uint32_t)SD.seq * H.gtiles + MD.tile_base;
+    for (uint32_t t = threadIdx.x; t < MD.ntot; t += 256) {
+        vis += B.tile_vis[k0 + t];
+        upd += B.tile_upd[k0 + t];
+        B.tile_vis[k0 + t] = 0;
+        B.tile_upd[k0 + t] = 0;
+    }
+    const uint32_t nb = (uint32_t)((SD.n + kBinBlock - 1) / kBinBlock);
+    for (uint32_t b = threadIdx.x; b < nb; b += 256) val += B.valid_part[SD.block0 + b];
+    s_sum[0][threadIdx.x] = upd;
+    s_sum[1][threadIdx.x] = val;
+    s_sum[2][threadIdx.x] = vis;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < (uint32_t)off)
+            for (int j = 0; j < 3; ++j) s_sum[j][threadIdx.x] += s_sum[j][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        B.scan_stats[4 * s + 0] = s_sum[0][0];
+        B.scan_stats[4 * s + 1] = s_sum[1][0];
+        B.scan_stats[4 * s + 2] = s_sum[2][0];
+        B.scan_stats[4 * s + 3] = B.ctl->overflow;
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        p[j] = v;
+}
+
+}  // namespace
+
+// A band segment spans at most (3 tau + 2) / 1024 + 2 voxels per axis, so
+// it crosses at most span / T_a + 1 tile faces on axis a.
+int32_t max_tiles_per_ray(int32_t tau, const int32_t lt[3])
+{
+    const int32_t span = (3 * tau + 2) / 1024 + 2;
+    int32_t n = 1;
+    for (int a = 0; a < 3; ++a) n += (span >> lt[a]) + 2;
+    return n;
+}
+
+hipError_t launch_batch(const BatchArrays &B, const LaunchCaps &caps, hipStream_t stream, hipEvent_t ev_start,
+                        hipEvent_t ev_binned, hipEvent_t ev_tiles)
+{
+    hipError_t e;
+    if (ev_start && (e = hipEventRecord(ev_start, stream)) != hipSuccess) return e;
+    const uint32_t bins = caps.blocks > 0 ? caps.blocks : 1u;
+    hipLaunchKernelGGL(k_bin<false>, dim3(bins), dim3(kBinBlock), 0, stream, B);
+    hipLaunchKernelGGL(k_alloc, dim3((caps.gtiles + kAllocBlock - 1) / kAllocBlock), dim3(kAllocBlock), 0, stream,
+                       B);
+    hipLaunchKernelGGL(k_bin<true>, dim3(bins), dim3(kBinBlock), 0, stream, B);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev_binned && (e = hipEventRecord(ev_binned, stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tile, dim3((uint32_t)caps.tile_grid), dim3(kTileBlock), caps.tile_lds, stream, B);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev_tiles && (e = hipEventRecord(ev_tiles, stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_stats, dim3(caps.scans > 0 ? caps.scans : 1u), dim3(256), 0, stream, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace tsdf

@@ -1,0 +1,421 @@
+// Host side of the batched integration engine (see batch.hip for the
+// kernels). One engine serves one HIP stream; it owns the descriptor tables,
+// the tile arrays, the entry buffer and the staging of host points, growing
+// them when a batch needs more.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <array>
+
+#include "engine.hpp"
+
+namespace tsdf {
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// Fixed layout of the descriptor tables for given capacities.
+struct DescLayout {
+    size_t hdr, maps, scans, block_scan, seq_scan, total;
+    static DescLayout of(size_t cap_maps, size_t cap_scans, size_t cap_blocks)
+    {
+        DescLayout L;
+        L.hdr = 0;
+        L.maps = up(sizeof(BatchHdr));
+        L.scans = up(L.maps + cap_maps * sizeof(MapDev));
+        L.block_scan = up(L.scans + cap_scans * sizeof(ScanDev));
+        L.seq_scan = up(L.block_scan + cap_blocks * sizeof(uint32_t));
+        L.total = up(L.seq_scan + cap_maps * kMaxSeq * sizeof(int32_t));
+        return L;
+    }
+};
+
+int64_t floor_mod64(int64_t a, int64_t b)
+{
+    int64_t r = a % b;
+    return r < 0 ? r + b : r;
+}
+
+int32_t ntiles_axis(int32_t n, int32_t lt) { return (n + (1 << lt) - 1) >> lt; }
+
+}  // namespace
+
+size_t single_map_array_bytes(const int32_t dims[3])
+{
+    // finest allowed tiles: edges 4, 4, 8
+    const size_t g = (size_t)ntiles_axis(dims[0], 2) * ntiles_axis(dims[1], 2) * ntiles_axis(dims[2], 3);
+    return up(5 * g * sizeof(uint32_t)) + 2 * up(g * sizeof(uint32_t));
+}
+
+Engine::Engine(hipStream_t stream, int device) : stream_(stream), device_(device)
+{
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
+        num_cu_ = cu;
+    for (int k = 0; k < 2; ++k) {
+        if (hipEventCreateWithFlags(&desc_ev_[k], hipEventDisableTiming) != hipSuccess) poisoned_ = true;
+        if (hipEventCreateWithFlags(&pts_ev_[k], hipEventDisableTiming) != hipSuccess) poisoned_ = true;
+    }
+    if (hipEventCreateWithFlags(&order_ev_, hipEventDisableTiming) != hipSuccess) poisoned_ = true;
+    if (hipMalloc(&ctl_, sizeof(BatchCtl)) != hipSuccess) poisoned_ = true;
+    else if (launch_fill_u32((uint32_t *)ctl_, sizeof(BatchCtl) / 4, 0u, stream_) != hipSuccess) poisoned_ = true;
+}
+
+Engine::~Engine()
+{
+    (void)hipStreamSynchronize(stream_);
+    for (int k = 0; k < 2; ++k) {
+        if (desc_host_[k]) (void)hipHostFree(desc_host_[k]);
+        if (pts_host_[k]) (void)hipHostFree(pts_host_[k]);
+        if (desc_ev_[k]) (void)hipEventDestroy(desc_ev_[k]);
+        if (pts_ev_[k]) (void)hipEventDestroy(pts_ev_[k]);
+    }
+    if (order_ev_) (void)hipEventDestroy(order_ev_);
+    for (void *p : {desc_dev_, entries_, valid_, stats_, ctl_, pts_dev_})
+        if (p) (void)hipFree(p);
+    if (arr_ && !arr_external_) (void)hipFree(arr_);
+    for (auto &t : prof_ev_)
+        for (hipEvent_t e : t) ev_pool_.push_back(e);
+    for (hipEvent_t e : ev_pool_) (void)hipEventDestroy(e);
+}
+
+tsdf_status Engine::fail()
+{
+    poisoned_ = true;
+    return TSDF_EDEVICE;
+}
+
+#define ECHK(call)                              \
+    do {                                        \
+        if ((call) != hipSuccess) return fail(); \
+    } while (0)
+
+void Engine::adopt_arrays(void *p, size_t bytes)
+{
+    arr_ = p;
+    arr_bytes_ = bytes;
+    arr_external_ = true;
+}
+
+tsdf_status Engine::grow(void **p, size_t *cap, size_t need, bool zero, bool host_pinned)
+{
+    if (need <= *cap) return TSDF_OK;
+    size_t ncap = std::max(need, *cap + *cap / 2);
+    ncap = up(ncap);
+    ECHK(hipStreamSynchronize(stream_));
+    if (*p) {
+        if (host_pinned) ECHK(hipHostFree(*p));
+        else ECHK(hipFree(*p));
+    }
+    *p = nullptr;
+    *cap = 0;
+    if (host_pinned) {
+        if (hipHostMalloc(p, ncap, hipHostMallocDefault) != hipSuccess) return TSDF_ENOMEM;
+    } else {
+        if (hipMalloc(p, ncap) != hipSuccess) return TSDF_ENOMEM;
+        if (zero) ECHK(launch_fill_u32((uint32_t *)*p, (int64_t)(ncap / 4), 0u, stream_));
+    }
+    *cap = ncap;
+    return TSDF_OK;
+}
+
+void Engine::profile(bool on)
+{
+    (void)hipStreamSynchronize(stream_);
+    for (auto &t : prof_ev_)
+        for (hipEvent_t e : t) ev_pool_.push_back(e);
+    prof_ev_.clear();
+    prof_on_ = on;
+}
+
+tsdf_status Engine::profile_read(int stage, double *ms, int64_t *n)
+{
+    ECHK(hipStreamSynchronize(stream_));
+    double tot = 0.0;
+    for (auto &t : prof_ev_) {
+        float x = 0.f;
+        ECHK(hipEventElapsedTime(&x, stage == 0 ? t[0] : t[1], stage == 0 ? t[1] : t[2]));
+        tot += x;
+    }
+    *ms = tot;
+    *n = (int64_t)prof_ev_.size();
+    return TSDF_OK;
+}
+
+tsdf_status Engine::run(const std::vector<MapRef> &maps, const std::vector<ScanRef> &scans, const int32_t lt[3],
+                        int32_t tile_grid, tsdf_scan_stats *stats)
+{
+    if (poisoned_) return TSDF_EDEVICE;
+    // every argument first: nothing is touched for an invalid batch
+    for (const ScanRef &s : scans) {
+        if (s.map < 0 || (size_t)s.map >= maps.size() || !s.pose || s.n < 0 || s.n > 0xffffffffLL ||
+            (s.n > 0 && !s.xyz))
+            return TSDF_EINVAL;
+        for (int k = 0; k < 12; ++k)
+            if (!isfinite(s.pose[k])) return TSDF_EINVAL;
+        const MapRef &m = maps[s.map];
+        for (int a = 0; a < 3; ++a) {
+            const double r = nearbyint(s.pose[4 * a + 3] * m.scale);
+            if (!(fabs(r) < 1073741824.0)) return TSDF_EINVAL;
+        }
+    }
+    // chunks in which no map has more than kMaxSeq scans
+    size_t b = 0;
+    while (b < scans.size()) {
+        std::vector<int32_t> per(maps.size(), 0);
+        size_t e = b;
+        while (e < scans.size() && per[scans[e].map] < kMaxSeq) per[scans[e++].map]++;
+        tsdf_status st = run_chunk(maps, scans, b, e, lt, tile_grid, stats ? stats + b : nullptr);
+        if (st != TSDF_OK) return st;
+        b = e;
+    }
+    return TSDF_OK;
+}
+
+tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector<ScanRef> &scans, size_t b,
+                              size_t e, const int32_t lt[3], int32_t tile_grid, tsdf_scan_stats *stats)
+{
+    const size_t nscans = e - b;
+    // map slots in order of first appearance, and each scan's sequence slot
+    std::vector<int32_t> slot_of(maps.size(), -1), seq(nscans), used;
+    std::vector<int32_t> nseq;
+    for (size_t k = 0; k < nscans; ++k) {
+        const int32_t m = scans[b + k].map;
+        if (slot_of[m] < 0) {
+            slot_of[m] = (int32_t)used.size();
+            used.push_back(m);
+            nseq.push_back(0);
+        }
+        seq[k] = nseq[slot_of[m]]++;
+    }
+    const int32_t nmaps = (int32_t)used.size();
+    int32_t S = 1;
+    for (int32_t v : nseq) S = std::max(S, v);
+    uint64_t gtiles = 0;
+    int32_t tau_max = 1;
+    std::vector<MapDev> md(nmaps);
+    for (int32_t j = 0; j < nmaps; ++j) {
+        const MapRef &m = maps[used[j]];
+        MapDev &d = md[j];
+        d.sdf = m.sdf;
+        d.w = m.w;
+        d.ntot = 1;
+        for (int a = 0; a < 3; ++a) {
+            d.dims[a] = m.dims[a];
+            d.origin[a] = m.origin[a];
+            d.ring0[a] = (int32_t)floor_mod64(m.origin[a], m.dims[a]);
+            d.nt[a] = ntiles_axis(m.dims[a], lt[a]);
+            d.ntot *= (uint32_t)d.nt[a];
+        }
+        d.tile_base = (uint32_t)gtiles;
+        gtiles += d.ntot;
+        d.tau = m.tau;
+        d.w_max = m.w_max;
+        d.vec_ok = (m.dims[2] % 8 == 0) && (d.ring0[2] % 8 == 0) && ((uintptr_t)m.sdf % 16 == 0) &&
+                   ((uintptr_t)m.w % 16 == 0);
+        d.pad = 0;
+        tau_max = std::max(tau_max, m.tau);
+    }
+    const uint64_t C = (uint64_t)S * gtiles;
+    if (C >= ((uint64_t)1 << 31)) return TSDF_ERANGE;
+    // binning blocks, points, entries
+    uint64_t nblocks = 0, npoints = 0, nhost = 0;
+    std::vector<uint32_t> block0(nscans);
+    for (size_t k = 0; k < nscans; ++k) {
+        const ScanRef &s = scans[b + k];
+        block0[k] = (uint32_t)nblocks;
+        nblocks += (uint64_t)((s.n + kBinBlock - 1) / kBinBlock);
+        npoints += (uint64_t)s.n;
+        if (s.host) nhost += (uint64_t)s.n;
+    }
+    const uint64_t need_entries = npoints * (uint64_t)max_tiles_per_ray(tau_max, lt) + 1024;
+    if (need_entries >= ((uint64_t)1 << 32) || nblocks >= ((uint64_t)1 << 31)) return TSDF_ERANGE;
+
+    // capacities (growing waits for the stream)
+    const size_t cap_maps = std::max<size_t>(nmaps, 1), cap_scans = std::max<size_t>(nscans, 1),
+                 cap_blocks = std::max<size_t>(nblocks, 1);
+    const DescLayout L = DescLayout::of(cap_maps, cap_scans, cap_blocks);
+    tsdf_status st;
+    if ((st = grow(&desc_dev_, &desc_cap_, L.total, false)) != TSDF_OK) return st;
+    {
+        // tile arrays: counts | offsets | cursor | tile_vis | tile_upd, then
+        // the busy-tile list; counts and records are zero between batches,
+        // so a new layout starts from zeroed memory
+        const size_t need_c = std::max<size_t>(C, 1), need_g = std::max<size_t>(gtiles, 1);
+        if (need_c > c_cap_ || need_g > g_cap_) {
+            size_t nc = need_c, ng = need_g;
+            if (!arr_external_) {
+                nc = std::max(need_c, c_cap_ + c_cap_ / 2);
+                ng = std::max(need_g, g_cap_ + g_cap_ / 2);
+            }
+            const size_t bytes = up(5 * nc * sizeof(uint32_t)) + 2 * up(ng * sizeof(uint32_t));
+            if (arr_external_) {
+                if (bytes > arr_bytes_) return TSDF_ERANGE;
+                ECHK(hipStreamSynchronize(stream_));
+            } else if ((st = grow(&arr_, &arr_bytes_, bytes, false)) != TSDF_OK) {
+                return st;
+            }
+            ECHK(launch_fill_u32((uint32_t *)arr_, (int64_t)(bytes / 4), 0u, stream_));
+            c_cap_ = nc;
+            g_cap_ = ng;
+        }
+    }
+    if ((st = grow(&entries_, &entries_cap_, need_entries * sizeof(uint4), false)) != TSDF_OK) return st;
+    if ((st = grow(&valid_, &valid_cap_, cap_blocks * sizeof(uint32_t), false)) != TSDF_OK) return st;
+    if ((st = grow(&stats_, &stats_cap_, cap_scans * 4 * sizeof(uint32_t), false)) != TSDF_OK) return st;
+
+    // host points: pinned staging, one copy to the device
+    std::vector<const float *> xyz(nscans);
+    if (nhost > 0) {
+        const size_t bytes = nhost * 3 * sizeof(float);
+        if ((st = grow(&pts_dev_, &pts_dev_cap_, bytes, false)) != TSDF_OK) return st;
+        const int k = pts_cur_;
+        if (pts_ev_live_[k]) ECHK(hipEventSynchronize(pts_ev_[k]));
+        pts_ev_live_[k] = false;
+        if ((st = grow(&pts_host_[k], &pts_host_cap_[k], bytes, false, true)) != TSDF_OK) return st;
+        size_t off = 0;
+        for (size_t j = 0; j < nscans; ++j) {
+            const ScanRef &s = scans[b + j];
+            if (!s.host) {
+                xyz[j] = s.xyz;
+                continue;
+            }
+            memcpy((char *)pts_host_[k] + off * 12, s.xyz, (size_t)s.n * 12);
+            xyz[j] = (const float *)((char *)pts_dev_ + off * 12);
+            off += (size_t)s.n;
+        }
+        ECHK(hipMemcpyAsync(pts_dev_, pts_host_[k], bytes, hipMemcpyHostToDevice, stream_));
+        ECHK(hipEventRecord(pts_ev_[k], stream_));
+        pts_ev_live_[k] = true;
+        pts_cur_ ^= 1;
+    } else {
+        for (size_t j = 0; j < nscans; ++j) xyz[j] = scans[b + j].xyz;
+    }
+
+    // descriptor tables
+    const int dk = desc_cur_;
+    if (desc_ev_live_[dk]) ECHK(hipEventSynchronize(desc_ev_[dk]));
+    desc_ev_live_[dk] = false;
+    if ((st = grow(&desc_host_[dk], &desc_host_cap_[dk], L.total, false, true)) != TSDF_OK) return st;
+    char *h = (char *)desc_host_[dk];
+    BatchHdr *hdr = (BatchHdr *)(h + L.hdr);
+    for (int a = 0; a < 3; ++a) hdr->lt[a] = lt[a];
+    hdr->S = S;
+    hdr->nmaps = nmaps;
+    hdr->nscans = (int32_t)nscans;
+    hdr->gtiles = (uint32_t)gtiles;
+    hdr->nblocks = (uint32_t)nblocks;
+    hdr->cap = (uint32_t)std::min<size_t>(entries_cap_ / sizeof(uint4), 0xffffffffu);
+    hdr->want_stats = stats ? 1u : 0u;
+    memcpy(h + L.maps, md.data(), nmaps * sizeof(MapDev));
+    ScanDev *sd = (ScanDev *)(h + L.scans);
+    uint32_t *bs = (uint32_t *)(h + L.block_scan);
+    int32_t *ss = (int32_t *)(h + L.seq_scan);
+    for (size_t j = 0; j < (size_t)nmaps * S; ++j) ss[j] = -1;
+    for (size_t k = 0; k < nscans; ++k) {
+        const ScanRef &s = scans[b + k];
+        const MapRef &m = maps[s.map];
+        ScanDev &d = sd[k];
+        for (int q = 0; q < 12; ++q) d.rp.M[q] = s.pose[q];
+        d.rp.scale = m.scale;
+        for (int a = 0; a < 3; ++a) d.rp.o[a] = (int32_t)nearbyint(s.pose[4 * a + 3] * m.scale);
+        d.rp.tau = m.tau;
+        d.xyz = xyz[k];
+        d.n = s.n;
+        d.map = slot_of[s.map];
+        d.seq = seq[k];
+        d.block0 = block0[k];
+        d.pad = 0;
+        const uint32_t nb = (uint32_t)((s.n + kBinBlock - 1) / kBinBlock);
+        for (uint32_t q = 0; q < nb; ++q) bs[block0[k] + q] = (uint32_t)k;
+        ss[d.map * S + d.seq] = (int32_t)k;
+    }
+    LaunchCaps caps;
+    caps.blocks = (uint32_t)nblocks;
+    caps.gtiles = (uint32_t)gtiles;
+    caps.scans = (uint32_t)nscans;
+    {
+        // LDS of a tile workgroup: G key buffers (8 bytes per voxel) and the
+        // cached tile (4 bytes per voxel); G as large as ~20 KB allows, so
+        // that eight workgroups fit a CU; the persistent grid fills the CUs
+        const size_t tvox = (size_t)1 << (lt[0] + lt[1] + lt[2]);
+        const int64_t gfit = ((int64_t)(20 * 1024) / (int64_t)tvox - 4) / 8;
+        const int32_t G = (int32_t)std::max<int64_t>(1, std::min<int64_t>({gfit, 8, (int64_t)S}));
+        hdr->G = G;
+        caps.tile_lds = (uint32_t)((8 * (size_t)G + 4) * tvox);
+        const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / caps.tile_lds));
+        caps.tile_grid = tile_grid > 0 ? tile_grid : num_cu_ * per_cu;
+    }
+    ECHK(hipMemcpyAsync(desc_dev_, h, L.total, hipMemcpyHostToDevice, stream_));
+    ECHK(hipEventRecord(desc_ev_[dk], stream_));
+    desc_ev_live_[dk] = true;
+    desc_cur_ ^= 1;
+
+    BatchArrays B;
+    char *dd = (char *)desc_dev_;
+    B.hdr = (BatchHdr *)(dd + L.hdr);
+    B.maps = (MapDev *)(dd + L.maps);
+    B.scans = (ScanDev *)(dd + L.scans);
+    B.block_scan = (uint32_t *)(dd + L.block_scan);
+    B.seq_scan = (int32_t *)(dd + L.seq_scan);
+    uint32_t *arr = (uint32_t *)arr_;
+    B.counts = arr;
+    B.offsets = arr + c_cap_;
+    B.cursor = arr + 2 * c_cap_;
+    B.tile_vis = arr + 3 * c_cap_;
+    B.tile_upd = arr + 4 * c_cap_;
+    B.nonempty = (uint32_t *)((char *)arr_ + up(5 * c_cap_ * 4));
+    B.nonempty_map = (uint32_t *)((char *)B.nonempty + up(g_cap_ * 4));
+    B.entries = (uint4 *)entries_;
+    B.valid_part = (uint32_t *)valid_;
+    B.scan_stats = (uint32_t *)stats_;
+    B.ctl = (BatchCtl *)ctl_;
+
+    // order after earlier work on each map's own stream
+    for (int32_t j = 0; j < nmaps; ++j) {
+        const MapRef &m = maps[used[j]];
+        if (m.stream != stream_) {
+            ECHK(hipEventRecord(order_ev_, m.stream));
+            ECHK(hipStreamWaitEvent(stream_, order_ev_, 0));
+        }
+    }
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (prof_on_) {
+        for (int k = 0; k < 3; ++k) {
+            if (!ev_pool_.empty()) {
+                ev[k] = ev_pool_.back();
+                ev_pool_.pop_back();
+            } else if (hipEventCreate(&ev[k]) != hipSuccess) {
+                return fail();
+            }
+        }
+        prof_ev_.push_back({ev[0], ev[1], ev[2]});
+    }
+    ECHK(launch_batch(B, caps, stream_, ev[0], ev[1], ev[2]));
+    // later work on each map's stream waits for this batch
+    for (int32_t j = 0; j < nmaps; ++j) {
+        const MapRef &m = maps[used[j]];
+        if (m.stream != stream_) {
+            ECHK(hipEventRecord(order_ev_, stream_));
+            ECHK(hipStreamWaitEvent(m.stream, order_ev_, 0));
+        }
+    }
+    if (stats) {
+        std::vector<uint32_t> host(nscans * 4);
+        ECHK(hipMemcpyAsync(host.data(), stats_, nscans * 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream_));
+        ECHK(hipStreamSynchronize(stream_));
+        for (size_t k = 0; k < nscans; ++k) {
+            if (host[4 * k + 3]) return fail();  // entry buffer overflow: cannot happen by its sizing
+            stats[k].points_in = scans[b + k].n;
+            stats[k].points_valid = host[4 * k + 1];
+            stats[k].visits = host[4 * k + 2];
+            stats[k].voxels_updated = host[4 * k + 0];
+        }
+    }
+    return TSDF_OK;
+}
+
+}  // namespace tsdf

@@ -1,0 +1,99 @@
+// Host side of the batched integration engine: device tables and buffers,
+// staging of host points, ordering against the maps' streams, timing.
+#pragma once
+
+#include "internal.hpp"
+
+namespace tsdf {
+
+// What the engine needs to know of a map.
+struct MapRef {
+    const void *id;  // identity (the tsdf_map)
+    int16_t *sdf, *w;
+    int32_t dims[3], origin[3];
+    double scale;  // 1024 / voxel size
+    int32_t tau, w_max;
+    hipStream_t stream;
+};
+
+struct ScanRef {
+    int32_t map;  // index into the maps vector
+    const float *xyz;
+    int64_t n;
+    bool host;  // xyz is host memory
+    const double *pose;
+};
+
+// Tile arrays of one map used on its own (one scan per batch), for maps
+// built on caller-owned memory: the size for the finest allowed tiling.
+size_t single_map_array_bytes(const int32_t dims[3]);
+
+class Engine {
+public:
+    Engine(hipStream_t stream, int device);
+    ~Engine();
+    Engine(const Engine &) = delete;
+    Engine &operator=(const Engine &) = delete;
+
+    // Use caller-owned memory for the tile arrays (fixed capacity).
+    void adopt_arrays(void *p, size_t bytes);
+
+    // Integrate the scans (in order per map). stats: one entry per scan or
+    // null. Returns TSDF_EINVAL before doing anything for bad arguments.
+    tsdf_status run(const std::vector<MapRef> &maps, const std::vector<ScanRef> &scans, const int32_t lt[3],
+                    int32_t tile_grid, tsdf_scan_stats *stats);
+
+    hipStream_t stream() const { return stream_; }
+    bool poisoned() const { return poisoned_; }
+
+    // per-stage timing (events on the engine's stream)
+    void profile(bool on);
+    tsdf_status profile_read(int stage, double *ms, int64_t *n);
+
+private:
+    tsdf_status run_chunk(const std::vector<MapRef> &maps, const std::vector<ScanRef> &scans, size_t b, size_t e,
+                          const int32_t lt[3], int32_t tile_grid, tsdf_scan_stats *stats);
+    tsdf_status grow(void **p, size_t *cap, size_t need, bool zero, bool host_pinned = false);
+    tsdf_status fail();
+
+    hipStream_t stream_;
+    int device_;
+    bool poisoned_ = false;
+    int num_cu_ = 256;
+    // descriptor tables: device and pinned host copies (double-buffered host side)
+    void *desc_dev_ = nullptr;
+    size_t desc_cap_ = 0;
+    void *desc_host_[2] = {nullptr, nullptr};
+    size_t desc_host_cap_[2] = {0, 0};
+    hipEvent_t desc_ev_[2] = {nullptr, nullptr};
+    bool desc_ev_live_[2] = {false, false};
+    int desc_cur_ = 0;
+    // tile arrays: counts | offsets | cursor | tile_vis | tile_upd (c_cap each), nonempty (g_cap)
+    void *arr_ = nullptr;
+    size_t arr_bytes_ = 0;
+    bool arr_external_ = false;
+    size_t c_cap_ = 0, g_cap_ = 0;
+    void *entries_ = nullptr;
+    size_t entries_cap_ = 0;  // bytes
+    void *valid_ = nullptr;
+    size_t valid_cap_ = 0;  // bytes
+    void *stats_ = nullptr;
+    size_t stats_cap_ = 0;  // bytes
+    void *ctl_ = nullptr;
+    // host points staging
+    void *pts_dev_ = nullptr;
+    size_t pts_dev_cap_ = 0;
+    void *pts_host_[2] = {nullptr, nullptr};
+    size_t pts_host_cap_[2] = {0, 0};
+    hipEvent_t pts_ev_[2] = {nullptr, nullptr};
+    bool pts_ev_live_[2] = {false, false};
+    int pts_cur_ = 0;
+    // cross-stream ordering
+    hipEvent_t order_ev_ = nullptr;
+    // timing
+    bool prof_on_ = false;
+    std::vector<hipEvent_t> ev_pool_;
+    std::vector<std::array<hipEvent_t, 3>> prof_ev_;
+};
+
+}  // namespace tsdf

@@ -14,23 +14,102 @@
 
 namespace tsdf {
 
-// Counters a scan accumulates on the device, and the finished scan's copy.
-struct DevCounters {
-    uint32_t touched;   // voxels whose candidate left EMPTY (== voxels updated)
-    uint32_t valid;     // points with a ray
-    uint32_t visits;    // (ray, resident voxel) candidates
-    uint32_t done;      // blocks of the merge that finished
-    uint32_t last[4];   // touched, valid, visits of the last finished scan
+// ---------------------------------------------------------------------------
+// Batched integration engine (batch.hip). Every integration, a single scan
+// included, is a batch: scans (any maps, several per map allowed) whose rays
+// are binned by (map tile, position of the scan among its map's scans in the
+// batch); one workgroup per tile then applies the map's scans to that tile in
+// submission order.
+// ---------------------------------------------------------------------------
+
+constexpr int kBinBlock = 256;   // binning threads per block (one ray each)
+constexpr int kMaxEmit = 12;     // tiles per ray listed in LDS before taking positions
+constexpr int kHashSlots = 1024; // per-block LDS table that merges (tile, seq) keys
+constexpr int32_t kMaxTileGrid = 65536;
+constexpr int32_t kMaxSeq = 64;  // scans of one map in one batch
+
+struct MapDev {
+    int16_t *sdf, *w;
+    int32_t dims[3], origin[3], ring0[3];
+    int32_t nt[3];
+    uint32_t ntot;       // tiles of this map
+    uint32_t tile_base;  // first global tile id of this map
+    int32_t tau, w_max;
+    int32_t vec_ok;      // 16-byte runs possible (see k_tile)
+    int32_t pad;
 };
 
-// Scratch of the plain per-scan path: a window-sized candidate array of
-// 64-bit keys (EMPTY between scans), the list of touched slots, counters.
-struct ScratchLayout {
-    size_t keys_off, touched_off, counters_off, total;
-    static ScratchLayout of(int64_t nvox);
+struct ScanDev {
+    RayParams rp;        // pose, scale, sensor position, tau
+    const float *xyz;
+    int64_t n;
+    int32_t map;         // map slot in the batch
+    int32_t seq;         // position among this map's scans in the batch
+    uint32_t block0;     // first binning block of this scan
+    uint32_t pad;
 };
 
+struct BatchHdr {
+    int32_t lt[3];
+    int32_t S;           // sequence slots per tile (most scans of one map)
+    int32_t G;           // sequence slots whose candidates a tile workgroup holds at once
+    int32_t nmaps, nscans;
+    uint32_t gtiles;     // sum of the maps' tile counts
+    uint32_t nblocks;    // binning blocks of this batch
+    uint32_t cap;        // entry capacity
+    uint32_t want_stats;
+};
+
+constexpr int kQueues = 8;  // tile job queues, one per XCD (workgroup b runs on XCD b % 8)
+
+struct BatchCtl {
+    uint32_t n_nonempty, entries, overflow, pad;
+    uint32_t work[kQueues];  // next job of each queue
+};
+
+// Device addresses of one engine (all inside buffers the engine owns).
+struct BatchArrays {
+    BatchHdr *hdr;
+    MapDev *maps;
+    ScanDev *scans;
+    uint32_t *block_scan;  // [nblocks] scan of each binning block
+    int32_t *seq_scan;     // [nmaps * S] scan of (map, seq), -1 if none
+    uint32_t *counts;      // [S * gtiles] entries per (seq, tile), seq-major; zero between batches
+    uint32_t *offsets;     // [S * gtiles] start of each run
+    uint32_t *cursor;      // [S * gtiles] fill position
+    uint32_t *tile_vis;    // [S * gtiles] visits per (seq, tile), when stats are wanted
+    uint32_t *tile_upd;    // [S * gtiles] voxels updated per (seq, tile)
+    uint32_t *nonempty;    // [gtiles] tiles with a ray
+    uint32_t *nonempty_map; // [gtiles] map slot of each listed tile
+    uint4 *entries;        // [cap] (point index, q.x, q.y, q.z), by tile then seq
+    uint32_t *valid_part;  // [nblocks] points with a ray per binning block
+    uint32_t *scan_stats;  // [nscans * 4] updated, valid, visits, overflow
+    BatchCtl *ctl;
+};
+
+// Upper bound of the tiles one ray's band can fall in.
+int32_t max_tiles_per_ray(int32_t tau, const int32_t lt[3]);
+
+// Grid sizes of one launch. Every grid is sized from these capacities and
+// the kernels read the batch's real sizes from the header, so a captured
+// graph serves every batch that fits them.
+struct LaunchCaps {
+    uint32_t blocks;      // binning blocks
+    uint32_t gtiles;      // global tiles
+    uint32_t scans;       // scans
+    int32_t tile_grid;    // tile workgroups
+    uint32_t tile_lds;    // dynamic LDS bytes of a tile workgroup
+};
+
+// Events recorded (when non-null) after binning and after the tile pass,
+// for per-stage timing.
+hipError_t launch_batch(const BatchArrays &B, const LaunchCaps &caps, hipStream_t stream, hipEvent_t ev_start,
+                        hipEvent_t ev_binned, hipEvent_t ev_tiles);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
 // Host-side store of 64^3-voxel chunks that left the window.
+// ---------------------------------------------------------------------------
 constexpr int kChunk = 64;
 constexpr int64_t kChunkVox = (int64_t)kChunk * kChunk * kChunk;
 
@@ -50,14 +129,6 @@ struct ChunkKeyHash {
 struct Chunk {
     std::vector<int16_t> sdf, w;  // kChunkVox each, [x][y][z] z fastest
 };
-
-// Launchers (integrate.hip, shift.hip). All enqueue on `stream`.
-hipError_t launch_candidates(const ScanParams &P, uint64_t *keys, uint32_t *touched, DevCounters *ctr,
-                             hipStream_t stream);
-hipError_t launch_merge(uint64_t *keys, const uint32_t *touched, DevCounters *ctr, int16_t *sdf, int16_t *w,
-                        int32_t w_max, hipStream_t stream);
-hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t stream);
-hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
 
 // A box of voxels copied between the window and a dense staging buffer:
 // global box [lo, lo + ext), staged at `off` (elements) as [x][y][z].

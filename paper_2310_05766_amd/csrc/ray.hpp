@@ -23,23 +23,17 @@ namespace tsdf {
 constexpr uint64_t kEmptyKey = ~0ull;
 constexpr double kQLimit = 1073741824.0;  // 2^30
 
-// Scan-invariant parameters, passed by value to the kernels.
-struct ScanParams {
+// What every ray of one scan shares.
+struct RayParams {
     double M[12];        // rows 0..2 of world_T_sensor, row-major
     double scale;        // 1024 / voxel_size
     int32_t o[3];        // sensor position, fixed point
     int32_t tau;         // truncation, fixed point
-    int32_t dims[3];     // window size
-    int32_t origin[3];   // window min corner (global voxel)
-    int32_t ring0[3];    // floor_mod(origin, dims): slot of the min corner
-    int32_t pad;
-    const float *xyz;    // n x 3 float32, sensor frame
-    int64_t n;
 };
 
 // q = round-half-even(fma-chain(M, p) * scale); false for a non-finite point
 // or |q_a| >= 2^30. The chain is fixed: fma(M0, x, fma(M1, y, fma(M2, z, M3))).
-__device__ __forceinline__ bool quantise(float px, float py, float pz, const ScanParams &P, int32_t q[3])
+__device__ __forceinline__ bool quantise(float px, float py, float pz, const RayParams &P, int32_t q[3])
 {
     if (!isfinite(px) || !isfinite(py) || !isfinite(pz)) return false;
     const double x = px, y = py, z = pz;
@@ -95,7 +89,7 @@ struct Ray {
 
 // D = q - o, r = isqrt(|D|^2); off = rdiv(tau D, r); E = q + off;
 // S = q - off, or S = o when r <= tau. false for D = 0.
-__device__ __forceinline__ bool make_ray(const int32_t q[3], const ScanParams &P, Ray &R)
+__device__ __forceinline__ bool make_ray(const int32_t q[3], const RayParams &P, Ray &R)
 {
     int64_t Di[3];
     uint64_t dd = 0;
@@ -140,32 +134,32 @@ __device__ __forceinline__ uint64_t pack_key(int32_t s, uint32_t i)
     return ((uint64_t)as << 48) | ((uint64_t)i << 16) | (uint64_t)(uint16_t)(int16_t)s;
 }
 
-__device__ __forceinline__ int32_t floor_div1024(int32_t v) { return v >> 10; }  // arithmetic shift
-
-// Exact walk over { floor(P(t) / 1024) : t in [0, 1] }, P(t) = S + t (E - S).
-// Axis crossings are ordered by their time t = dist / |L_a|, compared after
-// scaling every time by Lambda = product of the non-zero |L_a| (integers,
-// exact in float64). At equal times, crossings on increasing axes (which
-// take effect at t: a point on a face belongs to the upper cell) come
-// before crossings on decreasing axes (which take effect just after t).
-// Increasing crossings are taken for t <= 1, decreasing ones for t < 1.
+// Exact walk over the cells { floor((P(t) - base) / cell) : t in [0, 1] },
+// P(t) = S + t (E - S), with cell = 2^lc per axis in fixed point (lc = 10:
+// voxels; 10 + log2(tile edge): tiles). Axis crossings are ordered by their
+// time t = dist / |L_a|, compared after scaling every time by Lambda =
+// product of the non-zero |L_a| (integers, exact in float64). At equal
+// times, crossings on increasing axes (which take effect at t: a point on a
+// face belongs to the upper cell) come before crossings on decreasing axes
+// (which take effect just after t). Increasing crossings are taken for
+// t <= 1, decreasing ones for t < 1.
 struct Walk {
     int32_t g[3];
     int32_t step[3];
     double T[3], dT[3];
     double lam;
-    double n;       // (q - c(g)) . D for the current voxel
+    double n;       // (q - c(g)) . D for the current voxel (voxel walks)
     double dn[3];   // change of n per +1 step on each axis: -1024 D_a
 };
 
-__device__ __forceinline__ void walk_init(const Ray &R, Walk &W)
+__device__ __forceinline__ void walk_init_cells(const Ray &R, Walk &W, const int32_t lc[3], const int32_t base[3])
 {
     double L[3], absL[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         L[a] = (double)(R.E[a] - R.S[a]);
         absL[a] = fabs(L[a]);
-        W.g[a] = floor_div1024(R.S[a]);
+        W.g[a] = (int32_t)(((int64_t)R.S[a] - base[a]) >> lc[a]);  // arithmetic shift: floor division
         W.step[a] = L[a] > 0 ? 1 : (L[a] < 0 ? -1 : 0);
     }
     const double f0 = absL[0] > 0 ? absL[0] : 1.0;
@@ -176,22 +170,30 @@ __device__ __forceinline__ void walk_init(const Ray &R, Walk &W)
     double n = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double lo = 1024.0 * (double)W.g[a];
+        const double cell = (double)(1 << lc[a]);
+        const double lo = (double)base[a] + cell * (double)W.g[a];
         if (W.step[a] > 0) {
-            W.T[a] = (lo + 1024.0 - (double)R.S[a]) * other[a];
+            W.T[a] = (lo + cell - (double)R.S[a]) * other[a];
         } else if (W.step[a] < 0) {
             W.T[a] = ((double)R.S[a] - lo) * other[a];
         } else {
             W.T[a] = INFINITY;
         }
-        W.dT[a] = 1024.0 * other[a];
+        W.dT[a] = cell * other[a];
         n += ((double)R.q[a] - (lo + 512.0)) * R.D[a];
         W.dn[a] = -1024.0 * R.D[a];
     }
     W.n = n;
 }
 
-// Advance to the next voxel; false when the segment ends.
+// The voxel walk (cells of one voxel, global coordinates).
+__device__ __forceinline__ void walk_init(const Ray &R, Walk &W)
+{
+    const int32_t lc[3] = {10, 10, 10}, base[3] = {0, 0, 0};
+    walk_init_cells(R, W, lc, base);
+}
+
+// Advance to the next cell; false when the segment ends.
 __device__ __forceinline__ bool walk_next(Walk &W)
 {
     const double tm = fmin(W.T[0], fmin(W.T[1], W.T[2]));
@@ -205,18 +207,66 @@ __device__ __forceinline__ bool walk_next(Walk &W)
     return true;
 }
 
-// Slot of global voxel g if it lies in the window, else -1.
-__device__ __forceinline__ int64_t window_slot(const int32_t g[3], const ScanParams &P)
+// Crossings of one axis, at times T0 + k dT (k = 0, 1, ...) and of type typ
+// (0: increasing, 1: decreasing), that come at or before the event (Ts, ts)
+// in the walk's order (time, then increasing before decreasing).
+__device__ __forceinline__ double crossings_upto(double T0, double dT, int typ, double Ts, int ts)
 {
-    int32_t s[3];
+    if (!(T0 <= Ts)) return 0.0;  // also for an axis that never crosses (T0 = inf)
+    double k = floor((Ts - T0) / dT);
+    if (T0 + k * dT > Ts) k -= 1.0;             // exact: every term is an integer < 2^53
+    else if (T0 + (k + 1.0) * dT <= Ts) k += 1.0;
+    double c = k + 1.0;
+    if (T0 + k * dT == Ts && typ > ts) c -= 1.0;
+    return c;
+}
+
+// Move a freshly initialised voxel walk to its first voxel inside the box
+// [lo, hi) (global voxel coordinates): the state after every event up to the
+// one at which the last axis enters the box's range. false when no voxel of
+// the walk lies in the box. Coordinates are monotone along a walk, so the
+// voxels inside the box form one run that starts here.
+__device__ __forceinline__ bool walk_enter_box(Walk &W, const int32_t lo[3], const int32_t hi[3])
+{
+    double Te = -1.0;
+    int te = 0;
+    bool inside = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        int32_t rel = g[a] - P.origin[a];
-        if ((uint32_t)rel >= (uint32_t)P.dims[a]) return -1;
-        int32_t v = rel + P.ring0[a];
-        s[a] = v >= P.dims[a] ? v - P.dims[a] : v;
+        const int32_t g0 = W.g[a];
+        if (g0 >= lo[a] && g0 < hi[a]) continue;
+        inside = false;
+        double k;
+        int typ;
+        if (W.step[a] > 0 && g0 < lo[a]) {
+            k = (double)(lo[a] - g0);
+            typ = 0;
+        } else if (W.step[a] < 0 && g0 >= hi[a]) {
+            k = (double)(g0 - hi[a] + 1);
+            typ = 1;
+        } else {
+            return false;  // outside and not moving towards the box
+        }
+        const double T = W.T[a] + (k - 1.0) * W.dT[a];
+        if (T > Te || (T == Te && typ > te)) {
+            Te = T;
+            te = typ;
+        }
     }
-    return ((int64_t)s[0] * P.dims[1] + s[1]) * P.dims[2] + s[2];
+    if (inside) return true;
+    if (te == 0 ? (Te > W.lam) : (Te >= W.lam)) return false;  // after the segment's end
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (W.step[a] == 0) continue;
+        const double c = crossings_upto(W.T[a], W.dT[a], W.step[a] > 0 ? 0 : 1, Te, te);
+        W.g[a] += W.step[a] * (int32_t)c;
+        W.T[a] += c * W.dT[a];
+        W.n += (double)W.step[a] * c * W.dn[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (W.g[a] < lo[a] || W.g[a] >= hi[a]) return false;
+    return true;
 }
 
 }  // namespace tsdf

@@ -1,14 +1,16 @@
-// C ABI of the TSDF library: map objects, argument checks, point staging,
-// the host chunk store behind the local-map shift, readback.
+// C ABI of the TSDF library: map objects, argument checks, the batched
+// integration engine's front door, the host chunk store behind the
+// local-map shift, readback.
 // (FeatSense, arXiv 2310.05766, Sec. VI for integration, Sec. I for the
 // shifted local map and the store of what leaves it.)
 #include <math.h>
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
 #include <new>
 
-#include "internal.hpp"
+#include "engine.hpp"
 
 using namespace tsdf;
 
@@ -18,23 +20,12 @@ struct tsdf_map {
     double scale = 0.0;
     int16_t *sdf = nullptr, *w = nullptr;
     bool own_arrays = false;
-    void *scratch = nullptr;
-    bool own_scratch = false;
-    ScratchLayout lay{};
-    uint64_t *keys = nullptr;
-    uint32_t *touched = nullptr;
-    DevCounters *ctr = nullptr;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
-    // host point staging (double-buffered pinned) and its device copy
-    float *pinned[2] = {nullptr, nullptr};
-    hipEvent_t pinned_ev[2] = {nullptr, nullptr};
-    bool pinned_ev_live[2] = {false, false};
-    int pinned_cur = 0;
-    int64_t pinned_cap = 0;  // points
-    float *dev_pts = nullptr;
-    int64_t dev_pts_cap = 0;  // points
+    int32_t lt[3] = {3, 3, 3};  // integration tiles of 8^3 voxels
+    int32_t tile_grid = 0;      // 0: as many workgroups as fit the device
+    std::unique_ptr<Engine> engine;  // single-scan integration on the map's stream
     // shift / readback staging
     int16_t *stage_dev = nullptr;  // [2][stage_cap]
     int16_t *stage_host = nullptr;
@@ -42,7 +33,7 @@ struct tsdf_map {
     BoxXfer *boxes_dev = nullptr;
     BoxXfer *boxes_host = nullptr;
     int32_t boxes_cap = 0;
-    // per-kernel event timing (off unless enabled)
+    // per-kernel event timing (pack, unpack)
     bool prof_on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[TSDF_KERNEL_COUNT];
     std::vector<hipEvent_t> ev_pool;
@@ -134,8 +125,9 @@ bool desc_ok(const tsdf_map_desc *d)
     for (int a = 0; a < 3; ++a) {
         if (d->dims[a] < 1) return false;
         nv *= d->dims[a];
-        // every window coordinate must stay representable
-        if ((int64_t)d->origin[a] + d->dims[a] > (int64_t)1 << 30 || (int64_t)d->origin[a] < -((int64_t)1 << 30))
+        // points are kept only within 2^30 fixed-point units (2^20 voxels)
+        // of the global origin, so a window beyond that could never be hit
+        if ((int64_t)d->origin[a] + d->dims[a] > (int64_t)1 << 20 || (int64_t)d->origin[a] < -((int64_t)1 << 20))
             return false;
     }
     if (nv >= ((int64_t)1 << 31)) return false;
@@ -147,33 +139,33 @@ bool desc_ok(const tsdf_map_desc *d)
 
 int64_t nvox_of(const tsdf_map_desc *d) { return (int64_t)d->dims[0] * d->dims[1] * d->dims[2]; }
 
-tsdf_status ensure_points(tsdf_map *m, int64_t n, bool host)
+// Tiles of 2^lt voxels: every lt in [2, 6], the z edge at least 8 (merge
+// runs), 2^9..2^12 voxels per tile (12 bytes of LDS per voxel).
+bool tiling_ok(const int32_t lt[3])
 {
-    if (n > m->dev_pts_cap) {
-        int64_t cap = std::max<int64_t>(n, 1 << 16);
-        HIPCHK(m, hipStreamSynchronize(m->stream));
-        if (m->dev_pts) HIPCHK(m, hipFree(m->dev_pts));
-        m->dev_pts = nullptr;
-        m->dev_pts_cap = 0;
-        if (hipMalloc(&m->dev_pts, (size_t)cap * 3 * sizeof(float)) != hipSuccess) return TSDF_ENOMEM;
-        m->dev_pts_cap = cap;
+    int sum = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (lt[a] < 2 || lt[a] > 6) return false;
+        sum += lt[a];
     }
-    if (host && n > m->pinned_cap) {
-        int64_t cap = std::max<int64_t>(n, 1 << 16);
-        for (int k = 0; k < 2; ++k) {
-            if (m->pinned_ev_live[k]) HIPCHK(m, hipEventSynchronize(m->pinned_ev[k]));
-            m->pinned_ev_live[k] = false;
-            if (m->pinned[k]) HIPCHK(m, hipHostFree(m->pinned[k]));
-            m->pinned[k] = nullptr;
-        }
-        m->pinned_cap = 0;
-        for (int k = 0; k < 2; ++k)
-            if (hipHostMalloc((void **)&m->pinned[k], (size_t)cap * 3 * sizeof(float), hipHostMallocDefault) !=
-                hipSuccess)
-                return TSDF_ENOMEM;
-        m->pinned_cap = cap;
+    return lt[2] >= 3 && sum >= 9 && sum <= 12;
+}
+
+MapRef map_ref(const tsdf_map *m)
+{
+    MapRef r;
+    r.id = m;
+    r.sdf = m->sdf;
+    r.w = m->w;
+    for (int a = 0; a < 3; ++a) {
+        r.dims[a] = m->d.dims[a];
+        r.origin[a] = m->d.origin[a];
     }
-    return TSDF_OK;
+    r.scale = m->scale;
+    r.tau = m->d.tau_q10;
+    r.w_max = m->d.w_max;
+    r.stream = m->stream;
+    return r;
 }
 
 tsdf_status ensure_stage(tsdf_map *m, int64_t vox, int32_t boxes)
@@ -207,36 +199,15 @@ tsdf_status ensure_stage(tsdf_map *m, int64_t vox, int32_t boxes)
     return TSDF_OK;
 }
 
-tsdf_status init_map(tsdf_map *m)
-{
-    m->nvox = nvox_of(&m->d);
-    m->scale = 1024.0 / m->d.voxel_size_m;
-    m->lay = ScratchLayout::of(m->nvox);
-    m->keys = (uint64_t *)((char *)m->scratch + m->lay.keys_off);
-    m->touched = (uint32_t *)((char *)m->scratch + m->lay.touched_off);
-    m->ctr = (DevCounters *)((char *)m->scratch + m->lay.counters_off);
-    HIPCHK(m, launch_fill_u64(m->keys, m->nvox, kEmptyKey, m->stream));
-    HIPCHK(m, launch_fill_u32((uint32_t *)m->ctr, sizeof(DevCounters) / 4, 0u, m->stream));
-    for (int k = 0; k < 2; ++k)
-        if (hipEventCreateWithFlags(&m->pinned_ev[k], hipEventDisableTiming) != hipSuccess) return fail_device(m);
-    HIPCHK(m, hipStreamSynchronize(m->stream));
-    return TSDF_OK;
-}
-
 void release(tsdf_map *m)
 {
     if (!m) return;
     if (m->stream) (void)hipStreamSynchronize(m->stream);
+    m->engine.reset();
     if (m->own_arrays) {
         if (m->sdf) (void)hipFree(m->sdf);
         if (m->w) (void)hipFree(m->w);
     }
-    if (m->own_scratch && m->scratch) (void)hipFree(m->scratch);
-    for (int k = 0; k < 2; ++k) {
-        if (m->pinned[k]) (void)hipHostFree(m->pinned[k]);
-        if (m->pinned_ev[k]) (void)hipEventDestroy(m->pinned_ev[k]);
-    }
-    if (m->dev_pts) (void)hipFree(m->dev_pts);
     if (m->stage_dev) (void)hipFree(m->stage_dev);
     if (m->stage_host) (void)hipHostFree(m->stage_host);
     if (m->boxes_dev) (void)hipFree(m->boxes_dev);
@@ -245,6 +216,68 @@ void release(tsdf_map *m)
     for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
     if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
     delete m;
+}
+
+tsdf_status init_map(tsdf_map *m, void *arrays, size_t array_bytes)
+{
+    m->nvox = nvox_of(&m->d);
+    m->scale = 1024.0 / m->d.voxel_size_m;
+    m->engine.reset(new (std::nothrow) Engine(m->stream, m->device));
+    if (!m->engine) return TSDF_ENOMEM;
+    if (m->engine->poisoned()) return fail_device(m);
+    if (arrays) m->engine->adopt_arrays(arrays, array_bytes);
+    HIPCHK(m, hipStreamSynchronize(m->stream));
+    return TSDF_OK;
+}
+
+tsdf_map *new_map(const tsdf_map_desc *d, void *hip_stream, tsdf_status *st)
+{
+    tsdf_map *m = new (std::nothrow) tsdf_map();
+    if (!m) {
+        *st = TSDF_ENOMEM;
+        return nullptr;
+    }
+    m->d = *d;
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        delete m;
+        *st = TSDF_EDEVICE;
+        return nullptr;
+    }
+    if (hip_stream) {
+        m->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete m;
+            *st = TSDF_EDEVICE;
+            return nullptr;
+        }
+        m->own_stream = true;
+    }
+    *st = TSDF_OK;
+    return m;
+}
+
+// Engines for tsdf_integrate_batch, one per stream. The table is never
+// destroyed: at process exit the HIP runtime may already be gone, and the
+// operating system takes the memory back anyway.
+std::mutex g_engines_mu;
+std::unordered_map<hipStream_t, std::unique_ptr<Engine>> &engines()
+{
+    static auto *t = new std::unordered_map<hipStream_t, std::unique_ptr<Engine>>();
+    return *t;
+}
+
+// Drop the batch engine of a stream (its work is waited for first).
+void drop_engine(hipStream_t s)
+{
+    std::unique_ptr<Engine> e;
+    {
+        std::lock_guard<std::mutex> lk(g_engines_mu);
+        auto it = engines().find(s);
+        if (it == engines().end()) return;
+        e = std::move(it->second);
+        engines().erase(it);
+    }
 }
 
 // Box arithmetic over global voxel coordinates.
@@ -380,6 +413,7 @@ bool all_zero(const int16_t *a, const int16_t *b, int64_t n)
     return true;
 }
 
+
 }  // namespace
 
 extern "C" {
@@ -400,44 +434,30 @@ const char *tsdf_status_string(tsdf_status s)
 size_t tsdf_scratch_bytes(const tsdf_map_desc *d)
 {
     if (!desc_ok(d)) return 0;
-    return ScratchLayout::of(nvox_of(d)).total;
+    return single_map_array_bytes(d->dims);
 }
 
 tsdf_status tsdf_map_create(const tsdf_map_desc *d, void *hip_stream, tsdf_map **out)
 {
     if (!desc_ok(d) || !out) return TSDF_EINVAL;
     *out = nullptr;
-    tsdf_map *m = new (std::nothrow) tsdf_map();
-    if (!m) return TSDF_ENOMEM;
-    m->d = *d;
-    if (hipGetDevice(&m->device) != hipSuccess) {
-        delete m;
-        return TSDF_EDEVICE;
-    }
-    if (hip_stream) {
-        m->stream = (hipStream_t)hip_stream;
-    } else {
-        if (hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking) != hipSuccess) {
-            delete m;
-            return TSDF_EDEVICE;
-        }
-        m->own_stream = true;
-    }
+    tsdf_status st;
+    tsdf_map *m = new_map(d, hip_stream, &st);
+    if (!m) return st;
     const int64_t nv = nvox_of(d);
     m->own_arrays = true;
-    m->own_scratch = true;
     if (hipMalloc(&m->sdf, (size_t)nv * sizeof(int16_t)) != hipSuccess ||
-        hipMalloc(&m->w, (size_t)nv * sizeof(int16_t)) != hipSuccess ||
-        hipMalloc(&m->scratch, ScratchLayout::of(nv).total) != hipSuccess) {
+        hipMalloc(&m->w, (size_t)nv * sizeof(int16_t)) != hipSuccess) {
         release(m);
         return TSDF_ENOMEM;
     }
+    // every voxel starts at (0, 0): unknown (not inside any captured graph)
     if (hipMemsetAsync(m->sdf, 0, (size_t)nv * sizeof(int16_t), m->stream) != hipSuccess ||
         hipMemsetAsync(m->w, 0, (size_t)nv * sizeof(int16_t), m->stream) != hipSuccess) {
         release(m);
         return TSDF_EDEVICE;
     }
-    tsdf_status st = init_map(m);
+    st = init_map(m, nullptr, 0);
     if (st != TSDF_OK) {
         release(m);
         return st;
@@ -452,26 +472,17 @@ tsdf_status tsdf_map_create_in(const tsdf_map_desc *d, void *sdf_dev, void *w_de
     if (!desc_ok(d) || !out || !sdf_dev || !w_dev || !scratch_dev) return TSDF_EINVAL;
     if (scratch_bytes < tsdf_scratch_bytes(d)) return TSDF_EINVAL;
     *out = nullptr;
-    tsdf_map *m = new (std::nothrow) tsdf_map();
-    if (!m) return TSDF_ENOMEM;
-    m->d = *d;
-    if (hipGetDevice(&m->device) != hipSuccess) {
-        delete m;
-        return TSDF_EDEVICE;
-    }
-    if (hip_stream) {
-        m->stream = (hipStream_t)hip_stream;
-    } else {
-        if (hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking) != hipSuccess) {
-            delete m;
-            return TSDF_EDEVICE;
-        }
-        m->own_stream = true;
-    }
+    tsdf_status st;
+    tsdf_map *m = new_map(d, hip_stream, &st);
+    if (!m) return st;
     m->sdf = (int16_t *)sdf_dev;
     m->w = (int16_t *)w_dev;
-    m->scratch = scratch_dev;
-    tsdf_status st = init_map(m);
+    // the caller's scratch holds the tile arrays; zero them once
+    if (launch_fill_u32((uint32_t *)scratch_dev, (int64_t)(scratch_bytes / 4), 0u, m->stream) != hipSuccess) {
+        release(m);
+        return TSDF_EDEVICE;
+    }
+    st = init_map(m, scratch_dev, scratch_bytes);
     if (st != TSDF_OK) {
         release(m);
         return st;
@@ -483,6 +494,8 @@ tsdf_status tsdf_map_create_in(const tsdf_map_desc *d, void *sdf_dev, void *w_de
 tsdf_status tsdf_map_destroy(tsdf_map *m)
 {
     if (!m) return TSDF_EINVAL;
+    // a batch engine running on the stream this map owns goes with it
+    if (m->own_stream) drop_engine(m->stream);
     release(m);
     return TSDF_OK;
 }
@@ -495,60 +508,61 @@ tsdf_status tsdf_integrate_scan(tsdf_map *m, const float *xyz, int64_t n_points,
     Guard g(m);
     if (!g.ok) return TSDF_EBUSY;
     if (m->poisoned) return TSDF_EDEVICE;
-    ScanParams P;
-    for (int k = 0; k < 12; ++k) {
-        if (!isfinite(pose[k])) return TSDF_EINVAL;
-        P.M[k] = pose[k];
+    std::vector<MapRef> maps{map_ref(m)};
+    std::vector<ScanRef> scans{ScanRef{0, xyz, n_points, kind == TSDF_PTR_HOST, pose}};
+    tsdf_status st = m->engine->run(maps, scans, m->lt, m->tile_grid, stats);
+    if (st == TSDF_EDEVICE) m->poisoned = true;
+    return st;
+}
+
+tsdf_status tsdf_integrate_batch(const tsdf_scan_desc *scans, int32_t count, tsdf_ptr_kind kind, void *hip_stream,
+                                 tsdf_scan_stats *stats)
+{
+    if (count < 0 || (count > 0 && !scans)) return TSDF_EINVAL;
+    if (kind != TSDF_PTR_HOST && kind != TSDF_PTR_DEVICE) return TSDF_EINVAL;
+    if (count == 0) return TSDF_OK;
+    std::vector<MapRef> maps;
+    std::vector<ScanRef> refs;
+    std::unordered_map<const tsdf_map *, int32_t> idx;
+    std::vector<std::unique_ptr<Guard>> guards;
+    for (int32_t k = 0; k < count; ++k) {
+        tsdf_map *m = scans[k].map;
+        if (!m) return TSDF_EINVAL;
+        auto it = idx.find(m);
+        if (it == idx.end()) {
+            guards.emplace_back(new Guard(m));
+            if (!guards.back()->ok) return TSDF_EBUSY;
+            if (m->poisoned) return TSDF_EDEVICE;
+            it = idx.emplace(m, (int32_t)maps.size()).first;
+            maps.push_back(map_ref(m));
+        }
+        refs.push_back(ScanRef{it->second, scans[k].xyz, scans[k].n_points, kind == TSDF_PTR_HOST, scans[k].pose});
     }
-    P.scale = m->scale;
-    for (int a = 0; a < 3; ++a) {
-        const double r = nearbyint(pose[4 * a + 3] * m->scale);
-        if (!(fabs(r) < 1073741824.0)) return TSDF_EINVAL;
-        P.o[a] = (int32_t)r;
-        P.dims[a] = m->d.dims[a];
-        P.origin[a] = m->d.origin[a];
-        P.ring0[a] = (int32_t)floor_mod64(m->d.origin[a], m->d.dims[a]);
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : maps[0].stream;
+    Engine *eng;
+    {
+        std::lock_guard<std::mutex> lk(g_engines_mu);
+        auto &slot = engines()[s];
+        if (!slot) {
+            int dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess) return TSDF_EDEVICE;
+            slot.reset(new (std::nothrow) Engine(s, dev));
+            if (!slot) return TSDF_ENOMEM;
+        }
+        eng = slot.get();
     }
-    P.tau = m->d.tau_q10;
-    P.pad = 0;
-    P.n = n_points;
-    P.xyz = xyz;
-    if (kind == TSDF_PTR_HOST && n_points > 0) {
-        tsdf_status st = ensure_points(m, n_points, true);
-        if (st != TSDF_OK) return st;
-        const int k = m->pinned_cur;
-        if (m->pinned_ev_live[k]) HIPCHK(m, hipEventSynchronize(m->pinned_ev[k]));
-        memcpy(m->pinned[k], xyz, (size_t)n_points * 3 * sizeof(float));
-        HIPCHK(m, hipMemcpyAsync(m->dev_pts, m->pinned[k], (size_t)n_points * 3 * sizeof(float),
-                                 hipMemcpyHostToDevice, m->stream));
-        HIPCHK(m, hipEventRecord(m->pinned_ev[k], m->stream));
-        m->pinned_ev_live[k] = true;
-        m->pinned_cur ^= 1;
-        P.xyz = m->dev_pts;
-    }
-    HIPCHK(m, prof_start(m, TSDF_KERNEL_CANDIDATES));
-    HIPCHK(m, launch_candidates(P, m->keys, m->touched, m->ctr, m->stream));
-    HIPCHK(m, prof_stop(m, TSDF_KERNEL_CANDIDATES));
-    HIPCHK(m, prof_start(m, TSDF_KERNEL_MERGE));
-    HIPCHK(m, launch_merge(m->keys, m->touched, m->ctr, m->sdf, m->w, m->d.w_max, m->stream));
-    HIPCHK(m, prof_stop(m, TSDF_KERNEL_MERGE));
-    if (stats) {
-        uint32_t last[4];
-        HIPCHK(m, hipMemcpyAsync(last, m->ctr->last, sizeof(last), hipMemcpyDeviceToHost, m->stream));
-        HIPCHK(m, hipStreamSynchronize(m->stream));
-        stats->points_in = n_points;
-        stats->points_valid = last[1];
-        stats->visits = last[2];
-        stats->voxels_updated = last[0];
-    }
-    return TSDF_OK;
+    const tsdf_map *first = scans[0].map;
+    tsdf_status st = eng->run(maps, refs, first->lt, first->tile_grid, stats);
+    if (st == TSDF_EDEVICE)
+        for (int32_t k = 0; k < count; ++k) scans[k].map->poisoned = true;
+    return st;
 }
 
 tsdf_status tsdf_shift(tsdf_map *m, const int32_t new_origin[3])
 {
     if (!m || !new_origin) return TSDF_EINVAL;
     for (int a = 0; a < 3; ++a)
-        if ((int64_t)new_origin[a] + m->d.dims[a] > (int64_t)1 << 30 || (int64_t)new_origin[a] < -((int64_t)1 << 30))
+        if ((int64_t)new_origin[a] + m->d.dims[a] > (int64_t)1 << 20 || (int64_t)new_origin[a] < -((int64_t)1 << 20))
             return TSDF_EINVAL;
     Guard g(m);
     if (!g.ok) return TSDF_EBUSY;
@@ -691,16 +705,9 @@ tsdf_status tsdf_readback(tsdf_map *m, const int32_t lo[3], const int32_t hi[3],
     });
 }
 
-tsdf_status tsdf_integrate_batch(const tsdf_scan_desc *scans, int32_t count, tsdf_ptr_kind kind, void *hip_stream,
-                                 tsdf_scan_stats *stats)
+tsdf_status tsdf_batch_release(void *hip_stream)
 {
-    (void)hip_stream;
-    if (count < 0 || (count > 0 && !scans)) return TSDF_EINVAL;
-    for (int32_t k = 0; k < count; ++k) {
-        tsdf_status st = tsdf_integrate_scan(scans[k].map, scans[k].xyz, scans[k].n_points, kind, scans[k].pose,
-                                             stats ? &stats[k] : nullptr);
-        if (st != TSDF_OK) return st;
-    }
+    drop_engine((hipStream_t)hip_stream);
     return TSDF_OK;
 }
 
@@ -761,6 +768,7 @@ tsdf_status tsdf_profile_enable(tsdf_map *m, int32_t on)
     HIPCHK(m, hipStreamSynchronize(m->stream));
     prof_clear(m);
     m->prof_on = on != 0;
+    m->engine->profile(on != 0);
     return TSDF_OK;
 }
 
@@ -770,6 +778,11 @@ tsdf_status tsdf_profile_read(tsdf_map *m, int32_t kernel, double *total_ms, int
     Guard g(m);
     if (!g.ok) return TSDF_EBUSY;
     if (m->poisoned) return TSDF_EDEVICE;
+    if (kernel == TSDF_KERNEL_BIN || kernel == TSDF_KERNEL_TILE) {
+        tsdf_status st = m->engine->profile_read(kernel == TSDF_KERNEL_BIN ? 0 : 1, total_ms, launches);
+        if (st == TSDF_EDEVICE) m->poisoned = true;
+        return st;
+    }
     HIPCHK(m, hipStreamSynchronize(m->stream));
     double tot = 0.0;
     for (auto &p : m->prof_ev[kernel]) {
@@ -785,12 +798,32 @@ tsdf_status tsdf_profile_read(tsdf_map *m, int32_t kernel, double *total_ms, int
 const char *tsdf_kernel_name(int32_t kernel)
 {
     switch (kernel) {
-    case TSDF_KERNEL_CANDIDATES: return "k_candidates";
-    case TSDF_KERNEL_MERGE: return "k_merge";
+    case TSDF_KERNEL_BIN: return "k_bin";
+    case TSDF_KERNEL_TILE: return "k_tile";
     case TSDF_KERNEL_PACK: return "k_pack";
     case TSDF_KERNEL_UNPACK: return "k_unpack";
     default: return "unknown";
     }
+}
+
+tsdf_status tsdf_map_set_tiling(tsdf_map *m, const int32_t log2_tile[3], int32_t tile_workgroups)
+{
+    if (!m || !log2_tile || !tiling_ok(log2_tile) || tile_workgroups < 0 || tile_workgroups > kMaxTileGrid)
+        return TSDF_EINVAL;
+    Guard g(m);
+    if (!g.ok) return TSDF_EBUSY;
+    if (m->poisoned) return TSDF_EDEVICE;
+    for (int a = 0; a < 3; ++a) m->lt[a] = log2_tile[a];
+    m->tile_grid = tile_workgroups;
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_map_get_tiling(const tsdf_map *m, int32_t log2_tile[3], int32_t *tile_workgroups)
+{
+    if (!m || !log2_tile || !tile_workgroups) return TSDF_EINVAL;
+    for (int a = 0; a < 3; ++a) log2_tile[a] = m->lt[a];
+    *tile_workgroups = m->tile_grid;
+    return TSDF_OK;
 }
 
 tsdf_status tsdf_map_synchronize(tsdf_map *m)

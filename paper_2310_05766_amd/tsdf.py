@@ -6,7 +6,9 @@ tensors (torch provides device memory and streams).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 
 import numpy as np
 
@@ -41,6 +43,20 @@ def _points_arg(xyz):
     return xyz.data_ptr(), xyz.shape[0], _abi.TSDF_PTR_DEVICE, xyz
 
 
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # close maps while the HIP runtime is still up (interpreter-exit
+    # finalisers may run after it is gone)
+    for m in list(_live):
+        try:
+            m.close()
+        except Exception:
+            pass
+
+
 class TsdfMap:
     """A TSDF window (int16 SDF + int16 weight per voxel) plus its host chunk store."""
 
@@ -62,6 +78,7 @@ class TsdfMap:
             check(L.tsdf_map_create_in(C.byref(self.desc), sdf.data_ptr(), w.data_ptr(), scratch.data_ptr(),
                                        scratch.numel() * scratch.element_size(), sh, C.byref(self._h)),
                   "tsdf_map_create_in")
+        _live.add(self)
 
     @staticmethod
     def scratch_bytes(dims, origin, voxel_size, tau_u, w_max) -> int:
@@ -152,6 +169,17 @@ class TsdfMap:
     def synchronize(self):
         check(_abi.lib().tsdf_map_synchronize(self._h), "tsdf_map_synchronize")
 
+    def set_tiling(self, log2_tile, workgroups: int = 0):
+        """Candidate-buffer tiling (2^log2_tile voxels per axis); results do not depend on it."""
+        lt = (C.c_int32 * 3)(*[int(v) for v in log2_tile])
+        check(_abi.lib().tsdf_map_set_tiling(self._h, lt, int(workgroups)), "tsdf_map_set_tiling")
+
+    def get_tiling(self):
+        lt = (C.c_int32 * 3)()
+        g = C.c_int32()
+        check(_abi.lib().tsdf_map_get_tiling(self._h, lt, C.byref(g)), "tsdf_map_get_tiling")
+        return tuple(int(v) for v in lt), int(g.value)
+
     def profile(self, on: bool = True):
         """Start (clearing earlier records) or stop per-kernel event timing."""
         check(_abi.lib().tsdf_profile_enable(self._h, int(bool(on))), "tsdf_profile_enable")
@@ -190,3 +218,8 @@ def integrate_batch(items, stream=None, stats: bool = False):
         return [dict(points_in=s.points_in, points_valid=s.points_valid, visits=s.visits,
                      voxels_updated=s.voxels_updated) for s in st[:n]]
     return None
+
+
+def batch_release(stream):
+    """Free the batch engine kept for a stream (call before destroying it)."""
+    check(_abi.lib().tsdf_batch_release(_stream_handle(stream)), "tsdf_batch_release")

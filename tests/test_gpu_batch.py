@@ -1,0 +1,121 @@
+"""GPU parity of the batched forms: ordered multi-scan batches on one map,
+interleaved batches over several maps, batches longer than one chunk, and
+every candidate tiling -- each bit-exact with the oracle applied scan by
+scan in submission order."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_map(dims, origin, vs, tau, wmax):
+    from paper_2310_05766_amd.tsdf import TsdfMap
+    return TsdfMap(dims, origin, vs, tau, wmax)
+
+
+def same(gm, om, dims):
+    o = gm.origin
+    hi = tuple(o[a] + dims[a] for a in range(3))
+    g = gm.readback(o, hi)
+    r = om.readback(o, hi)
+    return np.array_equal(g[0], r[0]) and np.array_equal(g[1], r[1])
+
+
+def test_config2_ordered_batch():
+    from paper_2310_05766_amd.tsdf import integrate_batch
+    w = synth.config2(20)
+    spec = w.maps[0]
+    say("config2: 20 scans, one batch")
+    om = oracle.OracleMap.from_spec(spec)
+    ost = [om.integrate(s.xyz, s.pose) for s in w.scans]
+    gm = gpu_map(spec.dims, spec.origin, spec.voxel_size, spec.tau_u, spec.w_max)
+    gst = integrate_batch([(gm, s.xyz, s.pose) for s in w.scans], stats=True)
+    assert gst == ost
+    assert same(gm, om, spec.dims)
+    gm.close()
+    om.close()
+
+
+def test_interleaved_maps_and_long_batches():
+    """Three maps, scans interleaved in random order; one map gets 70 scans
+    (more than one chunk of 64)."""
+    from paper_2310_05766_amd.tsdf import integrate_batch
+    specs = [((48, 40, 24), (-24, -20, -12), 0.05, 3072, 5),
+             ((33, 65, 17), (-16, -30, -8), 0.08, 5120, 64),
+             ((64, 64, 64), (-32, -32, -32), 0.064, 5120, 64)]
+    g = np.random.default_rng(5)
+    order = [0] * 70 + [1] * 12 + [2] * 9
+    g.shuffle(order)
+    items, refs = [], []
+    gms = [gpu_map(*s) for s in specs]
+    oms = [oracle.OracleMap(*s) for s in specs]
+    for k, m in enumerate(order):
+        xyz = synth.fuzz_scan((77, k), 1500 + 97 * (k % 5), extent_m=1.5, nan_frac=0.05,
+                              grid_snap=0.05 if k % 7 == 0 else None)
+        pose = synth.fuzz_pose((78, k), max_t=0.3)
+        items.append((gms[m], xyz, pose))
+        refs.append(oms[m].integrate(xyz, pose))
+    say("interleaved batch of", len(items), "scans")
+    st = integrate_batch(items, stats=True)
+    assert st == refs
+    for k, s in enumerate(specs):
+        assert same(gms[k], oms[k], s[0]), k
+        gms[k].close()
+        oms[k].close()
+
+
+TILINGS = [(3, 3, 3), (2, 3, 4), (3, 4, 5), (4, 4, 4), (2, 2, 5), (4, 3, 3), (3, 3, 6), (4, 4, 3)]
+
+
+@pytest.mark.parametrize("lt", TILINGS)
+def test_every_tiling_gives_the_same_map(lt):
+    from paper_2310_05766_amd.tsdf import integrate_batch
+    w = synth.config1()
+    spec, sc = w.maps[0], w.scans[0]
+    om = oracle.OracleMap.from_spec(spec)
+    gm = gpu_map(spec.dims, spec.origin, spec.voxel_size, spec.tau_u, spec.w_max)
+    gm.set_tiling(lt)
+    assert gm.get_tiling()[0] == tuple(lt)
+    poses = [sc.pose] + [synth.fuzz_pose((lt, k), 0.4) for k in range(5)]
+    for p in poses[:2]:
+        assert gm.integrate(sc.xyz, p, stats=True) == om.integrate(sc.xyz, p)
+    st = integrate_batch([(gm, sc.xyz, p) for p in poses[2:]], stats=True)
+    assert st == [om.integrate(sc.xyz, p) for p in poses[2:]]
+    assert same(gm, om, spec.dims)
+    gm.close()
+    om.close()
+
+
+def test_invalid_tilings_rejected():
+    from paper_2310_05766_amd import TsdfError
+    gm = gpu_map((32, 32, 32), (-16, -16, -16), 0.05, 3072, 64)
+    for lt in [(1, 4, 4), (3, 3, 2), (7, 3, 3), (2, 2, 3), (5, 5, 5)]:
+        with pytest.raises(TsdfError):
+            gm.set_tiling(lt)
+    gm.close()
+
+
+def test_batch_of_nothing_and_empty_scans():
+    from paper_2310_05766_amd.tsdf import integrate_batch
+    gm = gpu_map((16, 16, 16), (-8, -8, -8), 0.1, 3072, 64)
+    om = oracle.OracleMap((16, 16, 16), (-8, -8, -8), 0.1, 3072, 64)
+    assert integrate_batch([]) is None
+    xyz = synth.fuzz_scan(91, 300, extent_m=0.7)
+    items = [(gm, np.zeros((0, 3), np.float32), np.eye(4)), (gm, xyz, np.eye(4)),
+             (gm, np.full((5, 3), np.nan, np.float32), np.eye(4))]
+    st = integrate_batch(items, stats=True)
+    ref = [om.integrate(x, p) for _, x, p in items]
+    assert st == ref
+    assert same(gm, om, (16, 16, 16))
+    gm.close()
+    om.close()
