@@ -125,6 +125,13 @@ tsdf_status tsdf_integrate_batch(const tsdf_scan_desc *scans, int32_t count, tsd
  * passed here. (Destroying a map drops the engine of the map's own stream.) */
 tsdf_status tsdf_batch_release(void *hip_stream);
 
+/* Launch mode of every integration (process wide). on = 1 (the default):
+ * each launch shape is captured once in a hipGraph (its five kernels, grid
+ * sizes rounded up to powers of two) and replayed; the kernels read the
+ * batch's real sizes from device memory. on = 0: direct kernel launches.
+ * Results are identical in both modes. */
+tsdf_status tsdf_set_graph_launch(int32_t on);
+
 /* --- inspection and helpers (no method arithmetic beyond what is named) --- */
 
 const char *tsdf_status_string(tsdf_status s);

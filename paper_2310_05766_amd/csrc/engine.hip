@@ -41,7 +41,46 @@ int64_t floor_mod64(int64_t a, int64_t b)
 
 int32_t ntiles_axis(int32_t n, int32_t lt) { return (n + (1 << lt) - 1) >> lt; }
 
+std::atomic<bool> g_graphs{true};
+
+uint32_t pow2_at_least(uint32_t v)
+{
+    uint32_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
 }  // namespace
+
+void Engine::set_graphs(bool on) { g_graphs.store(on); }
+bool Engine::graphs() { return g_graphs.load(); }
+
+hipError_t Engine::launch(const BatchArrays &B, const LaunchCaps &caps)
+{
+    for (const GraphEntry &g : graphs_)
+        if (memcmp(&g.B, &B, sizeof(B)) == 0 && memcmp(&g.caps, &caps, sizeof(caps)) == 0)
+            return hipGraphLaunch(g.exec, stream_);
+    // capture this shape: the kernels read every batch size from the device
+    // header, so the graph serves every later batch with these buffers and
+    // grid sizes
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = launch_batch(B, caps, stream_, nullptr, nullptr, nullptr);
+    e = hipStreamEndCapture(stream_, &graph);
+    if (le != hipSuccess) return le;
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    if (graphs_.size() >= 8) {
+        (void)hipGraphExecDestroy(graphs_.front().exec);
+        graphs_.erase(graphs_.begin());
+    }
+    graphs_.push_back(GraphEntry{B, caps, exec});
+    return hipGraphLaunch(exec, stream_);
+}
 
 size_t single_map_array_bytes(const int32_t dims[3])
 {
@@ -74,6 +113,7 @@ Engine::~Engine()
         if (pts_ev_[k]) (void)hipEventDestroy(pts_ev_[k]);
     }
     if (order_ev_) (void)hipEventDestroy(order_ev_);
+    for (GraphEntry &g : graphs_) (void)hipGraphExecDestroy(g.exec);
     for (void *p : {desc_dev_, entries_, valid_, stats_, ctl_, pts_dev_})
         if (p) (void)hipFree(p);
     if (arr_ && !arr_external_) (void)hipFree(arr_);
@@ -394,7 +434,16 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
         }
         prof_ev_.push_back({ev[0], ev[1], ev[2]});
     }
-    ECHK(launch_batch(B, caps, stream_, ev[0], ev[1], ev[2]));
+    if (prof_on_ || !graphs()) {
+        ECHK(launch_batch(B, caps, stream_, ev[0], ev[1], ev[2]));
+    } else {
+        // grid sizes rounded up to powers of two, so that few shapes exist
+        LaunchCaps gc = caps;
+        gc.blocks = pow2_at_least(std::max<uint32_t>(caps.blocks, 1));
+        gc.gtiles = pow2_at_least(std::max<uint32_t>(caps.gtiles, 1));
+        gc.scans = pow2_at_least(std::max<uint32_t>(caps.scans, 1));
+        ECHK(launch(B, gc));
+    }
     // later work on each map's stream waits for this batch
     for (int32_t j = 0; j < nmaps; ++j) {
         const MapRef &m = maps[used[j]];

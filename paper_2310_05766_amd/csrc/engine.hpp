@@ -48,6 +48,9 @@ public:
 
     // per-stage timing (events on the engine's stream)
     void profile(bool on);
+    // capture each launch shape once in a hipGraph and replay it
+    static void set_graphs(bool on);
+    static bool graphs();
     tsdf_status profile_read(int stage, double *ms, int64_t *n);
 
 private:
@@ -90,6 +93,14 @@ private:
     int pts_cur_ = 0;
     // cross-stream ordering
     hipEvent_t order_ev_ = nullptr;
+    // captured launches, keyed by buffers and (bucketed) grid sizes
+    struct GraphEntry {
+        BatchArrays B;
+        LaunchCaps caps;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs_;
+    hipError_t launch(const BatchArrays &B, const LaunchCaps &caps);
     // timing
     bool prof_on_ = false;
     std::vector<hipEvent_t> ev_pool_;

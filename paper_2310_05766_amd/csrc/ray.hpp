@@ -57,16 +57,20 @@ __device__ __forceinline__ uint64_t isqrt_u64(uint64_t n)
     return r;
 }
 
-// floor(a / d) for exact integers 0 <= a < 2^53, 0 < d < 2^34, given
-// inv_d = 1/d rounded; the estimate a * inv_d is off by less than 2^-36
-// relative to the quotient bound used, so one correction step is exact.
-// The quotient is first capped at cap (callers clamp it anyway).
+// Approximate 1/d (v_rcp_f64). Every quotient below is corrected exactly
+// afterwards, so its accuracy only decides how many correction steps run.
+__device__ __forceinline__ double approx_rcp(double d) { return __builtin_amdgcn_rcp(d); }
+
+// floor(a / d) for exact integers 0 <= a < 2^53, 0 < d < 2^34, from an
+// estimate a * inv_d (inv_d ~ 1/d): the estimate is capped at cap (callers
+// clamp the quotient there anyway), then corrected until k d <= a < (k+1) d
+// holds (every product is an exact integer below 2^53). The estimate is
+// within one of the quotient, so the loops run at most once.
 __device__ __forceinline__ double floor_div_exact(double a, double d, double inv_d, double cap)
 {
-    double k = floor(a * inv_d);
-    k = fmin(k, cap);
-    if (__fma_rn(k, d, d) <= a) k += 1.0;     // (k + 1) d <= a
-    else if (k * d > a) k -= 1.0;
+    double k = fmin(floor(a * inv_d), cap);
+    while (k * d > a) k -= 1.0;
+    while (k < cap && __fma_rn(k, d, d) <= a) k += 1.0;  // (k + 1) d <= a
     return k;
 }
 
@@ -104,7 +108,7 @@ __device__ __forceinline__ bool make_ray(const int32_t q[3], const RayParams &P,
     const uint64_t r = isqrt_u64(dd);
     R.r = (double)r;
     R.r2 = 2.0 * R.r;
-    R.inv_r2 = 1.0 / R.r2;
+    R.inv_r2 = approx_rcp(R.r2);
     const double tau = (double)P.tau;
     const bool near = (double)r <= tau;
 #pragma unroll
@@ -213,11 +217,12 @@ __device__ __forceinline__ bool walk_next(Walk &W)
 __device__ __forceinline__ double crossings_upto(double T0, double dT, int typ, double Ts, int ts)
 {
     if (!(T0 <= Ts)) return 0.0;  // also for an axis that never crosses (T0 = inf)
-    double k = floor((Ts - T0) / dT);
-    if (T0 + k * dT > Ts) k -= 1.0;             // exact: every term is an integer < 2^53
-    else if (T0 + (k + 1.0) * dT <= Ts) k += 1.0;
+    const double span = Ts - T0;   // exact: both are integers < 2^53
+    double k = floor(span * approx_rcp(dT));
+    while (k * dT > span) k -= 1.0;             // exact: every term is an integer < 2^53
+    while ((k + 1.0) * dT <= span) k += 1.0;
     double c = k + 1.0;
-    if (T0 + k * dT == Ts && typ > ts) c -= 1.0;
+    if (k * dT == span && typ > ts) c -= 1.0;
     return c;
 }
 

@@ -705,6 +705,12 @@ tsdf_status tsdf_readback(tsdf_map *m, const int32_t lo[3], const int32_t hi[3],
     });
 }
 
+tsdf_status tsdf_set_graph_launch(int32_t on)
+{
+    Engine::set_graphs(on != 0);
+    return TSDF_OK;
+}
+
 tsdf_status tsdf_batch_release(void *hip_stream)
 {
     drop_engine((hipStream_t)hip_stream);

@@ -223,3 +223,8 @@ def integrate_batch(items, stream=None, stats: bool = False):
 def batch_release(stream):
     """Free the batch engine kept for a stream (call before destroying it)."""
     check(_abi.lib().tsdf_batch_release(_stream_handle(stream)), "tsdf_batch_release")
+
+
+def set_graph_launch(on: bool):
+    """Replay captured hipGraphs (default) or launch kernels directly."""
+    check(_abi.lib().tsdf_set_graph_launch(int(bool(on))), "tsdf_set_graph_launch")

@@ -119,3 +119,53 @@ def test_batch_of_nothing_and_empty_scans():
     assert same(gm, om, (16, 16, 16))
     gm.close()
     om.close()
+
+
+def test_graph_replays_match_direct_launches():
+    """Captured graphs replayed many times, with eager work and syncs in
+    between, give the same maps as direct launches and as the oracle."""
+    from paper_2310_05766_amd.tsdf import integrate_batch, set_graph_launch
+    w = synth.config1()
+    spec, sc = w.maps[0], w.scans[0]
+    om = oracle.OracleMap.from_spec(spec)
+    maps = {}
+    try:
+        for mode in (True, False):
+            set_graph_launch(mode)
+            gm = gpu_map(spec.dims, spec.origin, spec.voxel_size, spec.tau_u, spec.w_max)
+            snaps = []
+            for k in range(6):
+                poses = [synth.fuzz_pose((k, j, 5), 0.4) for j in range(1 + k % 3)]
+                if k % 2:
+                    integrate_batch([(gm, sc.xyz[: 4000 + 1000 * j], p) for j, p in enumerate(poses)])
+                else:
+                    for j, p in enumerate(poses):
+                        gm.integrate(sc.xyz[: 4000 + 1000 * j], p)
+                gm.synchronize()
+                snaps.append(gm.readback_window())
+                if mode:
+                    for j, p in enumerate(poses):
+                        om.integrate(sc.xyz[: 4000 + 1000 * j], p)
+                    ref = om.readback(spec.origin, tuple(spec.origin[a] + spec.dims[a] for a in range(3)))
+                    assert np.array_equal(snaps[-1][0], ref[0]) and np.array_equal(snaps[-1][1], ref[1]), k
+            maps[mode] = snaps
+            gm.close()
+    finally:
+        set_graph_launch(True)
+    for a, b in zip(maps[True], maps[False]):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    om.close()
+
+
+def test_autotuner_candidates_agree(tmp_path, monkeypatch):
+    import torch
+    from paper_2310_05766_amd.autotune import autotune
+    monkeypatch.setenv("XDG_CACHE_HOME", str(tmp_path))
+    w = synth.config1()
+    spec, sc = w.maps[0], w.scans[0]
+    sample = [(torch.from_numpy(sc.xyz).to("cuda"), synth.fuzz_pose((3, k), 0.3)) for k in range(4)]
+    torch.cuda.synchronize()
+    best = autotune(spec, sample, mode="batch", reps=1)
+    assert tuple(best["lt"]) in [tuple(c["lt"]) for c in best["candidates"]]
+    again = autotune(spec, sample, mode="batch", reps=1)
+    assert again["cached"] and tuple(again["lt"]) == tuple(best["lt"])
