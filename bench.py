@@ -141,6 +141,57 @@ def shift_leg(torch, TsdfMap, synth):
             "host_link_GBps": moved / t / 1e9}
 
 
+def serving_leg(torch, synth, seconds: float, speedup: float, pool: int = 8):
+    """Config-5 serving: 48 sessions (maps 256^3 / 384^3 / 512x512x256 at
+    6.4 cm), 16x1024 scans arriving Poisson at 10 Hz per session. A real-time
+    replay of `seconds` of arrivals gives p50/p99 latency; a replay compressed
+    `speedup` times gives the peak served rate; the same scans integrated one
+    call per scan, back to back, give the plain rate. Each session's scans
+    cycle through a pool of `pool` pre-generated scans (same shapes and
+    sizes), so that scan generation never stalls the replay."""
+    from paper_2310_05766_amd.serve import GpuExecutor, Server, latency_summary, replay
+    from paper_2310_05766_amd.tsdf import TsdfMap
+
+    sessions = synth.config5(n_sessions=48, duration_s=seconds)
+    scans = {}
+    for s in sessions:
+        for k in range(pool):
+            sc = s.scan(k)
+            scans[(s.sid, k)] = (sc.xyz, sc.pose)
+
+    def scans_of(sid, k):
+        return scans[(sid, k % pool)]
+
+    trace = [(s.sid, s.spec, s.arrivals) for s in sessions]
+    n_scans = sum(len(s.arrivals) for s in sessions)
+    out = {"sessions": len(sessions), "scans": n_scans, "offered_scans_per_s": n_scans / seconds,
+           "pool_scans_per_session": pool}
+    for name, sp in (("realtime", 1.0), ("compressed", speedup)):
+        ex = GpuExecutor(lanes=2)
+        srv = Server(ex, budget_bytes=200 * 10 ** 9, lanes=2, max_batch=64)
+        t0 = time.perf_counter()
+        recs = replay(srv, trace, scans_of, speedup=sp)
+        wall = time.perf_counter() - t0
+        ex.close()
+        out[name] = dict(latency_summary(recs), speedup=sp, wall_s=wall, scans_per_s=len(recs) / wall,
+                         batches=srv.batches)
+    # plain: one call per scan, arrival order, one stream, maps resident
+    st = torch.cuda.Stream()
+    maps = {s.sid: TsdfMap.from_spec(s.spec, stream=st) for s in sessions}
+    events = sorted((t, s.sid, k) for s in sessions for k, t in enumerate(s.arrivals))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _, sid, k in events:
+        x, p = scans_of(sid, k)
+        maps[sid].integrate(x, p)
+    st.synchronize()
+    wall = time.perf_counter() - t0
+    for m in maps.values():
+        m.close()
+    out["plain_scans_per_s"] = len(events) / wall
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +201,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle baseline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-shift", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--profile-only", action="store_true", help="warmup + timed steps only (for rocprofv3)")
     ap.add_argument("--plain-only", action="store_true", help="with --profile-only: per-scan calls only")
     args = ap.parse_args()
@@ -268,6 +321,10 @@ def main():
     gm.close()
 
     shift = None if args.no_shift else shift_leg(torch, TsdfMap, synth)
+    serving = None
+    if not args.no_serving:
+        log("serving (config 5)")
+        serving = serving_leg(torch, synth, args.serving_seconds, speedup=1000.0)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -320,6 +377,7 @@ def main():
             "algorithmic_bytes_scan_by_scan": B_scans,
         },
         "shift": shift,
+        "serving": serving,
         "cpu_baseline": cpu,
         "sources_sha256": sources_digest(),
     }

@@ -1,0 +1,146 @@
+"""Scheduler logic of the serving loop on the CPU: admission by memory
+budget, per-session arrival order across lanes and batches, session close,
+rejection of malformed scans. The executor is an oracle-backed stand-in, so
+every map can be checked against integrating its scans alone, in order."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2310_05766_amd.serve import Server, latency_summary, replay
+
+
+class OracleExecutor:
+    """Executes each batch immediately with the oracle (a CPU stand-in for
+    the GPU executor: same interface, same semantics)."""
+
+    def __init__(self):
+        self.launches = []
+
+    @staticmethod
+    def map_bytes(spec):
+        return 4 * spec.n_voxels
+
+    def create_map(self, spec, lane):
+        return oracle.OracleMap.from_spec(spec)
+
+    def launch(self, lane, items):
+        self.launches.append((lane, len(items)))
+        return [m.integrate(x, p) for m, x, p in items]
+
+    def done(self, token):
+        return True
+
+    def token_stats(self, token):
+        return token
+
+    def release_map(self, m):
+        self.released = getattr(self, "released", 0) + 1
+
+
+def small_spec(k):
+    dims = [(24, 24, 24), (32, 16, 16), (16, 16, 32)][k % 3]
+    return synth.MapSpec(dims, tuple(-d // 2 for d in dims), 0.1, 3072, 3)  # small w_max: order matters
+
+
+def scan(sid, k):
+    return synth.fuzz_scan((sid, k), 400, extent_m=1.0, nan_frac=0.02), synth.fuzz_pose((sid, k, 9), 0.3)
+
+
+def alone(spec, scans):
+    m = oracle.OracleMap.from_spec(spec)
+    for x, p in scans:
+        m.integrate(x, p)
+    return m
+
+
+def window(m, spec):
+    return m.readback(spec.origin, tuple(spec.origin[a] + spec.dims[a] for a in range(3)))
+
+
+def test_mix_equals_alone_in_arrival_order():
+    ex = OracleExecutor()
+    srv = Server(ex, budget_bytes=1 << 30, lanes=3, max_batch=5, max_per_session=2)
+    specs = {sid: small_spec(sid) for sid in range(7)}
+    for sid, sp in specs.items():
+        srv.open_session(sid, sp)
+    order = [sid for sid in range(7) for _ in range(6)]
+    np.random.default_rng(1).shuffle(order)
+    counts = {sid: 0 for sid in specs}
+    for sid in order:
+        x, p = scan(sid, counts[sid])
+        srv.submit(sid, counts[sid], x, p)
+        counts[sid] += 1
+        if counts[sid] % 2 == 0:
+            srv.step()
+    maps = {sid: srv.sessions[sid].map for sid in specs}
+    srv.drain()
+    assert len(srv.completed) == len(order)
+    assert max(n for _, n in ex.launches) <= 5
+    for sid, sp in specs.items():
+        ref = alone(sp, [scan(sid, k) for k in range(6)])
+        a, b = window(maps[sid], sp), window(ref, sp)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), sid
+    # per session, completion order is arrival order
+    for sid in specs:
+        ks = [r.k for r in srv.completed if r.sid == sid]
+        assert ks == sorted(ks)
+
+
+def test_admission_waits_for_memory():
+    ex = OracleExecutor()
+    sp = small_spec(0)
+    budget = 2 * OracleExecutor.map_bytes(sp) + 10  # two maps at a time
+    srv = Server(ex, budget_bytes=budget, lanes=2)
+    for sid in range(4):
+        srv.open_session(sid, sp)
+    assert [srv.admitted(s) for s in range(4)] == [True, True, False, False]
+    for sid in range(4):
+        x, p = scan(sid, 0)
+        srv.submit(sid, 0, x, p)
+    srv.step()
+    assert not srv.admitted(2)
+    srv.close_session(0)
+    srv.step()
+    assert srv.admitted(2) and not srv.admitted(3)
+    srv.close_session(1)
+    srv.close_session(2)
+    srv.close_session(3)
+    srv.drain()
+    assert len(srv.completed) == 4 and srv.used == 0
+    assert [s for _, s in srv.admit_log] == [0, 1, 2, 3]
+    with pytest.raises(ValueError):
+        srv.open_session(9, synth.MapSpec((512, 512, 512), (0, 0, 0), 0.1, 3072, 3))
+
+
+def test_malformed_scans_rejected_and_closed_sessions():
+    ex = OracleExecutor()
+    sp = small_spec(1)
+    srv = Server(ex, budget_bytes=1 << 30)
+    srv.open_session(0, sp)
+    x, p = scan(0, 0)
+    bad = p.copy()
+    bad[1, 2] = np.nan
+    with pytest.raises(ValueError):
+        srv.submit(0, 0, x, bad)
+    assert srv.pending() == 0
+    srv.submit(0, 0, x, p)
+    srv.close_session(0)
+    with pytest.raises(ValueError):
+        srv.submit(0, 1, x, p)
+    srv.drain()
+    assert srv.sessions[0].closed and srv.used == 0
+
+
+def test_replay_trace_time_compressed():
+    ex = OracleExecutor()
+    sessions = [(sid, small_spec(sid), np.sort(np.random.default_rng(sid).uniform(0, 0.3, size=5)))
+                for sid in range(5)]
+    srv = Server(ex, budget_bytes=3 * OracleExecutor.map_bytes(small_spec(0)) + 100, lanes=2)
+    recs = replay(srv, sessions, scan, speedup=4.0)
+    assert len(recs) == 25
+    s = latency_summary(recs)
+    assert s["scans"] == 25 and s["p99_ms"] >= s["p50_ms"] >= 0
+    for sid, sp, _ in sessions:
+        ks = [r.k for r in recs if r.sid == sid]
+        assert ks == sorted(ks)
