@@ -205,14 +205,28 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--profile-only", action="store_true", help="warmup + timed steps only (for rocprofv3)")
     ap.add_argument("--plain-only", action="store_true", help="with --profile-only: per-scan calls only")
+    ap.add_argument("--batched-only", action="store_true", help="with --profile-only: batched steps only")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only a plain 256 MiB device copy, three times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(every workload fits one MI355X; sharding is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported "
+              "(every workload fits one MI355X; maps and sessions would shard whole across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = 256 * 1024 * 1024
+        a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {n} bytes three times")
+        return
 
     import synth
     from paper_2310_05766_amd.tsdf import TsdfMap, integrate_batch
@@ -228,19 +242,6 @@ def main():
     # timing events all live on it
     stream = torch.cuda.Stream()
     gm = TsdfMap.from_spec(spec, stream=stream)
-
-    # per-scan counts (state independent): U, visits, valid points; on the
-    # fresh map, the voxels any scan touches (the union) are those with w > 0
-    stats = [gm.integrate(x, p, stats=True) for x, p in zip(dev, poses)]
-    U_step = sum(s["voxels_updated"] for s in stats)
-    N_step = sum(s["points_in"] for s in stats)
-    visits_step = sum(s["visits"] for s in stats)
-    _sdf_ptr, w_ptr, _st = gm.device_arrays()
-    w_view = torch.empty(spec.n_voxels, dtype=torch.int16, device="cuda")
-    _copy_device(torch, w_view, w_ptr, spec.n_voxels * 2)
-    U_union = int((w_view > 0).sum().item())
-    del w_view
-    n_scans = len(dev)
 
     batch_items = [(gm, x, p) for x, p in zip(dev, poses)]
 
@@ -261,18 +262,35 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
+    if args.profile_only:
+        # the launches a profiler should see, and nothing else: warmup and
+        # timed steps of the chosen form on the fresh map
+        parts = []
+        if not args.batched_only:
+            parts.append(("plain", timed(step_plain)))
+        if not args.plain_only:
+            parts.append(("batched", timed(step_batched)))
+        log("profile-only: " + ", ".join(f"{k} {v * 1e3 / args.steps:.3f} ms/step" for k, v in parts))
+        gm.close()
+        return
+
+    # per-scan counts (state independent): U, visits, valid points; on the
+    # fresh map, the voxels any scan touches (the union) are those with w > 0
+    stats = [gm.integrate(x, p, stats=True) for x, p in zip(dev, poses)]
+    U_step = sum(s["voxels_updated"] for s in stats)
+    N_step = sum(s["points_in"] for s in stats)
+    visits_step = sum(s["visits"] for s in stats)
+    _sdf_ptr, w_ptr, _st = gm.device_arrays()
+    w_view = torch.empty(spec.n_voxels, dtype=torch.int16, device="cuda")
+    _copy_device(torch, w_view, w_ptr, spec.n_voxels * 2)
+    U_union = int((w_view > 0).sum().item())
+    del w_view
+    n_scans = len(dev)
+
     log("plain per-scan steps")
     dt_plain = timed(step_plain)
-    if args.profile_only and args.plain_only:
-        log(f"profile-only: plain {dt_plain * 1e3 / args.steps:.3f} ms/step")
-        gm.close()
-        return
     log("batched steps")
     dt = timed(step_batched)
-    if args.profile_only:
-        log(f"profile-only: plain {dt_plain * 1e3 / args.steps:.3f} ms/step, batched {dt * 1e3 / args.steps:.3f} ms/step")
-        gm.close()
-        return
 
     def stage_times(step, reps):
         gm.profile(True)
@@ -288,25 +306,29 @@ def main():
 
     log("kernel timing")
     kt_plain = stage_times(step_plain, max(3, args.steps // 4))
-    # batched launches go through the stream's batch engine: time them with
-    # torch events on the same stream (the map's stream is that stream)
-    kt = {}
-    reps = max(3, args.steps // 2)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    for a, b in ev:
-        a.record(stream)
+    # batched launches: stage events of the stream's batch engine
+    from paper_2310_05766_amd.tsdf import batch_profile, batch_profile_read
+    # (the same K steps again, launched directly: stage events sit between
+    # kernels, so these launches are not graph replays)
+    batch_profile(stream, True)
+    for _ in range(args.steps):
         step_batched()
-        b.record(stream)
-    torch.cuda.synchronize()
-    launch_ms = [a.elapsed_time(b) for a, b in ev]
-    kt["batch"] = {"total_ms": sum(launch_ms), "launches": reps, "avg_us": 1e3 * sum(launch_ms) / reps}
+    kt = {}
+    for name, stage in (("bin", "bin"), ("k_tile", "tile"), ("stats", "stats"), ("launch", "launch")):
+        ms, n = batch_profile_read(stream, stage)
+        kt[name] = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / max(n, 1)}
+    batch_profile(stream, False)
 
     # algorithmic bytes: 12 per point (no-return slots included), 128 per
     # pose, 8 per voxel update (int16 sdf + int16 w read once, written once)
     B_scans = 12.0 * N_step + 128.0 * n_scans + 8.0 * U_step           # scan by scan
     B_batch = 12.0 * N_step + 128.0 * n_scans + 8.0 * U_union          # one pass over the batch
-    achieved = B_batch / (kt["batch"]["avg_us"] * 1e-6) / 1e9
-    traffic = read_traffic("batch", "config2")
+    # the tile pass holds the method's map traffic (each touched voxel read
+    # and written once per batch) and reads the poses; points are read by
+    # the binning kernels
+    B_tile = 128.0 * n_scans + 8.0 * U_union
+    achieved = B_tile / (kt["k_tile"]["avg_us"] * 1e-6) / 1e9
+    traffic = read_traffic("k_tile", "config2_batch")
 
     # synchronous per-scan latency (plain path)
     log("latency")
@@ -367,14 +389,19 @@ def main():
         "kernels": kt,
         "roofline": {
             "bound": "hbm",
-            "kernel": "batch (k_bin + k_alloc + k_tile on one stream)",
+            "kernel": "k_tile",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "algorithmic_bytes_per_launch": B_batch,
+            "algorithmic_bytes_per_launch": B_tile,
+        },
+        "step_roofline": {
+            "algorithmic_bytes": B_batch,
             "algorithmic_bytes_scan_by_scan": B_scans,
+            "gpu_us": kt["launch"]["avg_us"],
+            "achieved_GBps": B_batch / (kt["launch"]["avg_us"] * 1e-6) / 1e9,
         },
         "shift": shift,
         "serving": serving,

@@ -132,6 +132,15 @@ tsdf_status tsdf_batch_release(void *hip_stream);
  * Results are identical in both modes. */
 tsdf_status tsdf_set_graph_launch(int32_t on);
 
+/* Stage timing of the batch engine of a stream (which exists once a batch
+ * ran on it): while on, each batch launch is bracketed by HIP events on that
+ * stream (and launched directly, not from a graph). Stages: 0 binning (ray
+ * counts, runs, fill), 1 tile pass (candidates, minimum, Eq. (1)/(2)),
+ * 2 per-scan counts, 3 the whole launch. _read waits for the stream and
+ * returns the summed milliseconds and the number of launches. */
+tsdf_status tsdf_batch_profile(void *hip_stream, int32_t on);
+tsdf_status tsdf_batch_profile_read(void *hip_stream, int32_t stage, double *total_ms, int64_t *launches);
+
 /* --- inspection and helpers (no method arithmetic beyond what is named) --- */
 
 const char *tsdf_status_string(tsdf_status s);

@@ -20,7 +20,8 @@ EXPORTS = (
     "tsdf_shift", "tsdf_readback", "tsdf_integrate_batch", "tsdf_status_string", "tsdf_map_origin",
     "tsdf_map_device_arrays", "tsdf_recentre_origin", "tsdf_store_info", "tsdf_map_synchronize",
     "tsdf_profile_enable", "tsdf_profile_read", "tsdf_kernel_name", "tsdf_map_set_tiling",
-    "tsdf_map_get_tiling", "tsdf_batch_release", "tsdf_set_graph_launch",
+    "tsdf_map_get_tiling", "tsdf_batch_release", "tsdf_set_graph_launch", "tsdf_batch_profile",
+    "tsdf_batch_profile_read",
 )
 KERNELS = {"k_bin": 0, "k_tile": 1, "k_pack": 2, "k_unpack": 3}
 
@@ -97,6 +98,10 @@ def lib():
     L.tsdf_map_set_tiling.argtypes = [vp, i32p, C.c_int32]
     L.tsdf_map_get_tiling.restype = st
     L.tsdf_map_get_tiling.argtypes = [vp, i32p, C.POINTER(C.c_int32)]
+    L.tsdf_batch_profile.restype = st
+    L.tsdf_batch_profile.argtypes = [vp, C.c_int32]
+    L.tsdf_batch_profile_read.restype = st
+    L.tsdf_batch_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.tsdf_set_graph_launch.restype = st
     L.tsdf_set_graph_launch.argtypes = [C.c_int32]
     L.tsdf_batch_release.restype = st

@@ -177,7 +177,8 @@ tsdf_status Engine::profile_read(int stage, double *ms, int64_t *n)
     double tot = 0.0;
     for (auto &t : prof_ev_) {
         float x = 0.f;
-        ECHK(hipEventElapsedTime(&x, stage == 0 ? t[0] : t[1], stage == 0 ? t[1] : t[2]));
+        const int a = stage == 3 ? 0 : stage, b = stage == 3 ? 3 : stage + 1;
+        ECHK(hipEventElapsedTime(&x, t[a], t[b]));
         tot += x;
     }
     *ms = tot;
@@ -422,9 +423,9 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
             ECHK(hipStreamWaitEvent(stream_, order_ev_, 0));
         }
     }
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (prof_on_) {
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             if (!ev_pool_.empty()) {
                 ev[k] = ev_pool_.back();
                 ev_pool_.pop_back();
@@ -432,10 +433,11 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
                 return fail();
             }
         }
-        prof_ev_.push_back({ev[0], ev[1], ev[2]});
+        prof_ev_.push_back({ev[0], ev[1], ev[2], ev[3]});
     }
     if (prof_on_ || !graphs()) {
         ECHK(launch_batch(B, caps, stream_, ev[0], ev[1], ev[2]));
+        if (ev[3]) ECHK(hipEventRecord(ev[3], stream_));
     } else {
         // grid sizes rounded up to powers of two, so that few shapes exist
         LaunchCaps gc = caps;

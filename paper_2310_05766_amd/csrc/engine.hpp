@@ -51,6 +51,8 @@ public:
     // capture each launch shape once in a hipGraph and replay it
     static void set_graphs(bool on);
     static bool graphs();
+    // stage 0: binning (count, runs, fill), 1: tile pass, 2: per-scan counts,
+    // 3: the whole launch
     tsdf_status profile_read(int stage, double *ms, int64_t *n);
 
 private:
@@ -104,7 +106,7 @@ private:
     // timing
     bool prof_on_ = false;
     std::vector<hipEvent_t> ev_pool_;
-    std::vector<std::array<hipEvent_t, 3>> prof_ev_;
+    std::vector<std::array<hipEvent_t, 4>> prof_ev_;
 };
 
 }  // namespace tsdf

@@ -267,6 +267,13 @@ std::unordered_map<hipStream_t, std::unique_ptr<Engine>> &engines()
     return *t;
 }
 
+Engine *engine_of(hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_engines_mu);
+    auto it = engines().find(s);
+    return it == engines().end() ? nullptr : it->second.get();
+}
+
 // Drop the batch engine of a stream (its work is waited for first).
 void drop_engine(hipStream_t s)
 {
@@ -703,6 +710,21 @@ tsdf_status tsdf_readback(tsdf_map *m, const int32_t lo[3], const int32_t hi[3],
         }
         return TSDF_OK;
     });
+}
+
+tsdf_status tsdf_batch_profile(void *hip_stream, int32_t on)
+{
+    Engine *e = engine_of((hipStream_t)hip_stream);
+    if (!e) return TSDF_EINVAL;
+    e->profile(on != 0);
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_batch_profile_read(void *hip_stream, int32_t stage, double *total_ms, int64_t *launches)
+{
+    Engine *e = engine_of((hipStream_t)hip_stream);
+    if (!e || stage < 0 || stage > 3 || !total_ms || !launches) return TSDF_EINVAL;
+    return e->profile_read(stage, total_ms, launches);
 }
 
 tsdf_status tsdf_set_graph_launch(int32_t on)

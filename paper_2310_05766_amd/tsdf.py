@@ -228,3 +228,19 @@ def batch_release(stream):
 def set_graph_launch(on: bool):
     """Replay captured hipGraphs (default) or launch kernels directly."""
     check(_abi.lib().tsdf_set_graph_launch(int(bool(on))), "tsdf_set_graph_launch")
+
+
+BATCH_STAGES = {"bin": 0, "tile": 1, "stats": 2, "launch": 3}
+
+
+def batch_profile(stream, on: bool = True):
+    """Per-stage event timing of the batch engine of a stream."""
+    check(_abi.lib().tsdf_batch_profile(_stream_handle(stream), int(bool(on))), "tsdf_batch_profile")
+
+
+def batch_profile_read(stream, stage: str):
+    """(total_ms, launches) of one stage ("bin", "tile", "stats", "launch")."""
+    ms, n = C.c_double(), C.c_int64()
+    check(_abi.lib().tsdf_batch_profile_read(_stream_handle(stream), BATCH_STAGES[stage], C.byref(ms), C.byref(n)),
+          "tsdf_batch_profile_read")
+    return float(ms.value), int(n.value)

@@ -99,7 +99,7 @@ def config3(n_scans: int = 200) -> Workload:
         xyz = S.scan(scene, pose, 16, 1024, (-15.0, 15.0), 0.01, (0.0, 30.0), 300 + k)
         scans.append(Scan(xyz, pose, 16, 1024))
     # the window origin is placed by the recentre rule from the first pose;
-    # the origin here is only a placeholder the driver overwrites.
+    # the origin here is only a placeholder the caller overwrites.
     m = MapSpec((512, 512, 128), (0, 0, 0), 0.05, 3072, 64)
     return Workload("ring-buffer loop 16x1024 -> 512x512x128 @ 5 cm", [m], scans,
                     extra={"recentre_vox": 64, "chunk": 64})

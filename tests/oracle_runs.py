@@ -12,7 +12,7 @@ import synth
 
 
 def pool_size() -> int:
-    # the GPU machine gives one GPU job 16 host cores; stay well inside that
+    # a one-GPU test host may give a job as few as 16 cores; stay well inside that
     return max(1, min(8, (os.cpu_count() or 2) - 1))
 
 

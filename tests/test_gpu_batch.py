@@ -46,6 +46,31 @@ def test_config2_ordered_batch():
     om.close()
 
 
+def test_config2_full_batch_as_benchmarked():
+    """The benchmark's launch shape: all 50 OS1-128 scans of the sequence as
+    one ordered batch, points already in device memory, on a stream of its
+    own, graph launch on; the second batch replays the captured graph."""
+    import torch
+    from paper_2310_05766_amd.tsdf import TsdfMap, integrate_batch, set_graph_launch
+    w = synth.config2()
+    spec = w.maps[0]
+    set_graph_launch(True)
+    st = torch.cuda.Stream()
+    dev = [torch.from_numpy(s.xyz).to("cuda") for s in w.scans]
+    torch.cuda.synchronize()
+    gm = TsdfMap.from_spec(spec, stream=st)
+    om = oracle.OracleMap.from_spec(spec)
+    for rep in range(2):
+        say("config2: batch of 50, pass", rep)
+        integrate_batch([(gm, x, s.pose) for x, s in zip(dev, w.scans)], stream=st)
+        for s in w.scans:
+            om.integrate(s.xyz, s.pose)
+        gm.synchronize()
+        assert same(gm, om, spec.dims), rep
+    gm.close()
+    om.close()
+
+
 def test_interleaved_maps_and_long_batches():
     """Three maps, scans interleaved in random order; one map gets 70 scans
     (more than one chunk of 64)."""
