@@ -69,7 +69,9 @@ size_t tsdf_scratch_bytes(const tsdf_map_desc *d);
 tsdf_status tsdf_map_create(const tsdf_map_desc *d, void *hip_stream, tsdf_map **out);
 
 /* As tsdf_map_create, on caller-owned device memory: sdf_dev and w_dev hold
- * nx*ny*nz int16 each (layout above; the caller initialises them), and
+ * nx*ny*nz int16 each (layout above; the caller initialises them to a state
+ * the method can reach, 0 <= w <= w_max and |sdf| <= tau_q10 per voxel, e.g.
+ * all zero: other contents give unspecified values, never a fault), and
  * scratch_dev holds at least tsdf_scratch_bytes(d) bytes. They must outlive
  * the map; the library never frees them. */
 tsdf_status tsdf_map_create_in(const tsdf_map_desc *d, void *sdf_dev, void *w_dev, void *scratch_dev,

@@ -37,13 +37,48 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t key)
     return (key * 2654435761u) >> (32 - 10);  // kHashSlots = 2^10
 }
 
+// Second half of an entry record: what the tile pass needs of the ray
+// beyond its point, r = isqrt(|D|^2) and the band offsets off = E - q (both
+// exact: r < 2^32, |off_a| <= tau < 2^15), and the voxel crossings per axis
+// (each < 2^7) up to the event that entered the tile.
+__device__ __forceinline__ uint4 entry_ray(const Ray &R, uint32_t cpack)
+{
+    const uint32_t o0 = (uint32_t)(R.E[0] - R.q[0]) & 0xffffu, o1 = (uint32_t)(R.E[1] - R.q[1]) & 0xffffu,
+                   o2 = (uint32_t)(R.E[2] - R.q[2]) & 0xffffu;
+    return make_uint4((uint32_t)R.r, o0 | o1 << 16, o2 | (cpack & 0xffffu) << 16, cpack >> 16);
+}
+
+// The ray of an entry record: as make_ray gives it, without its divisions.
+__device__ __forceinline__ void ray_of_entry(const uint4 &ra, const uint4 &rb, const int32_t o[3], int32_t tau,
+                                             Ray &R, int32_t c[3])
+{
+    const int32_t off[3] = {(int16_t)(rb.y & 0xffffu), (int16_t)(rb.y >> 16), (int16_t)(rb.z & 0xffffu)};
+    R.q[0] = (int32_t)ra.y;
+    R.q[1] = (int32_t)ra.z;
+    R.q[2] = (int32_t)ra.w;
+    R.r = (double)rb.x;
+    R.r2 = 2.0 * R.r;
+    R.inv_r2 = approx_rcp(R.r2);
+    const bool near = R.r <= (double)tau;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        R.D[a] = (double)((int64_t)R.q[a] - o[a]);
+        R.E[a] = R.q[a] + off[a];
+        R.S[a] = near ? o[a] : R.q[a] - off[a];
+    }
+    c[0] = (int32_t)((rb.z >> 16) & 0xffu);
+    c[1] = (int32_t)(rb.z >> 24);
+    c[2] = (int32_t)(rb.w & 0xffu);
+}
+
 template <bool kFill>
 __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
 {
     __shared__ uint32_t h_key[kHashSlots];  // key + 1; 0 = free
     __shared__ uint32_t h_cnt[kHashSlots];
     __shared__ uint32_t h_base[kFill ? kHashSlots : 1];
-    __shared__ uint16_t s_slot[kFill ? kMaxEmit * kBinBlock : 1];
+    // per emitted entry: hash slot | crossing counts << 10, and rank
+    __shared__ uint32_t s_slot[kFill ? kMaxEmit * kBinBlock : 1];
     __shared__ uint16_t s_rank[kFill ? kMaxEmit * kBinBlock : 1];
     __shared__ uint32_t s_valid;
     const BatchHdr H = *B.hdr;
@@ -69,7 +104,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
     const int64_t i = (int64_t)(blockIdx.x - SD.block0) * kBinBlock + threadIdx.x;
     const RayParams rp = SD.rp;
     Ray R;
-    Walk W;
+    Walk W, Wv;  // the walk on the tile grid; the voxel walk's start (fill)
     bool active = false;
     int32_t q[3] = {0, 0, 0};
     if (i < SD.n) {
@@ -81,11 +116,14 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
             const int32_t lc[3] = {10 + H.lt[0], 10 + H.lt[1], 10 + H.lt[2]};
             const int32_t base[3] = {1024 * MD.origin[0], 1024 * MD.origin[1], 1024 * MD.origin[2]};
             walk_init_cells(R, W, lc, base);
+            if (kFill) walk_init(R, Wv);
         }
     }
     const uint32_t valid = active ? 1u : 0u;
     const uint32_t key0 = (uint32_t)SD.seq * H.gtiles + MD.tile_base;
     int ne = 0;
+    double t_in = -1.0;  // event that entered the current tile (none for the first)
+    int typ_in = 0;
     while (active) {
         if ((uint32_t)W.g[0] < (uint32_t)MD.nt[0] && (uint32_t)W.g[1] < (uint32_t)MD.nt[1] &&
             (uint32_t)W.g[2] < (uint32_t)MD.nt[2]) {
@@ -100,22 +138,35 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
                 }
                 h = (h + 1u) & (kHashSlots - 1u);
             }
+            // voxel crossings of each axis up to the event that entered
+            // this tile: the tile pass resumes the voxel walk there
+            uint32_t cpack = 0;
+            if (kFill && t_in >= 0.0) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    cpack |= (uint32_t)crossings_upto(Wv.T[a], Wv.dT[a], Wv.step[a] > 0 ? 0 : 1, t_in, typ_in)
+                             << (8 * a);
+            }
             if (slot != 0xffffu && (!kFill || ne < kMaxEmit)) {
                 const uint32_t rank = atomicAdd(&h_cnt[slot], 1u);
                 if (kFill) {
-                    s_slot[ne * kBinBlock + threadIdx.x] = (uint16_t)slot;
+                    s_slot[ne * kBinBlock + threadIdx.x] = slot | cpack << 10;
                     s_rank[ne * kBinBlock + threadIdx.x] = (uint16_t)rank;
                 }
             } else if (kFill) {  // table full or very long band: straight to the tile's run
                 const uint32_t pos = atomicAdd(&B.cursor[key], 1u);
-                if (pos < H.cap) B.entries[pos] = make_uint4((uint32_t)i, (uint32_t)q[0], (uint32_t)q[1], (uint32_t)q[2]);
-                else atomicOr(&B.ctl->overflow, 1u);
+                if (pos < H.cap) {
+                    B.entries[pos] = make_uint4((uint32_t)i, (uint32_t)q[0], (uint32_t)q[1], (uint32_t)q[2]);
+                    B.entries2[pos] = entry_ray(R, cpack);
+                } else {
+                    atomicOr(&B.ctl->overflow, 1u);
+                }
             } else {
                 atomicAdd(&B.counts[key], 1u);
             }
             ++ne;
         }
-        active = walk_next(W);
+        active = walk_next_event(W, t_in, typ_in);
     }
     if (!kFill && valid) atomicAdd(&s_valid, 1u);
     __syncthreads();
@@ -137,9 +188,14 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
     const uint4 rec = make_uint4((uint32_t)i, (uint32_t)q[0], (uint32_t)q[1], (uint32_t)q[2]);
     const int nl = ne < kMaxEmit ? ne : kMaxEmit;
     for (int k = 0; k < nl; ++k) {
-        const uint32_t pos = h_base[s_slot[k * kBinBlock + threadIdx.x]] + s_rank[k * kBinBlock + threadIdx.x];
-        if (pos < H.cap) B.entries[pos] = rec;
-        else atomicOr(&B.ctl->overflow, 1u);
+        const uint32_t sc = s_slot[k * kBinBlock + threadIdx.x];
+        const uint32_t pos = h_base[sc & 1023u] + s_rank[k * kBinBlock + threadIdx.x];
+        if (pos < H.cap) {
+            B.entries[pos] = rec;
+            B.entries2[pos] = entry_ray(R, sc >> 10);
+        } else {
+            atomicOr(&B.ctl->overflow, 1u);
+        }
     }
 }
 
@@ -159,19 +215,34 @@ __device__ __forceinline__ int32_t map_of_tile(const BatchArrays &B, int32_t nma
 // consecutive in sequence order; the tile is listed as busy. Runs may lie in
 // any order, so they are handed out by atomic allocation, one atomic per
 // block and counter (same-address device atomics serialise; a block prefix
-// keeps them few).
+// keeps them few). Four lanes share a tile, each summing a quarter of its
+// sequence slots, so that the chains of count loads stay short.
+constexpr int kAllocTiles = kAllocBlock / 4;
+
 __global__ __launch_bounds__(kAllocBlock) void k_alloc(BatchArrays B)
 {
     __shared__ uint32_t s_wc[kAllocBlock / 64], s_wn[kAllocBlock / 64];
     __shared__ uint32_t s_base_c, s_base_n;
     const BatchHdr H = *B.hdr;
-    const uint32_t t = blockIdx.x * kAllocBlock + threadIdx.x;
-    if (blockIdx.x * kAllocBlock >= H.gtiles) return;
-    const uint32_t wave = threadIdx.x / 64;
+    if (blockIdx.x * kAllocTiles >= H.gtiles) return;
+    const uint32_t t = blockIdx.x * kAllocTiles + threadIdx.x / 4;
+    const uint32_t part = threadIdx.x & 3u, wave = threadIdx.x / 64;
+    const int per = (H.S + 3) / 4;
+    const int s_lo = (int)part * per, s_hi = min(H.S, s_lo + per);
     uint32_t c = 0;
     if (t < H.gtiles)
-        for (int sq = 0; sq < H.S; ++sq) c += B.counts[(uint32_t)sq * H.gtiles + t];
-    uint32_t pc = c, pn = c != 0;
+        for (int sq = s_lo; sq < s_hi; ++sq) c += B.counts[(uint32_t)sq * H.gtiles + t];
+    // inclusive prefix of the four parts of a tile, and the tile's total
+    uint32_t pq = c;
+    {
+        uint32_t a = (uint32_t)__shfl_up((int)pq, 1);
+        if (part >= 1) pq += a;
+        a = (uint32_t)__shfl_up((int)pq, 2);
+        if (part >= 2) pq += a;
+    }
+    const uint32_t tile_c = (uint32_t)__shfl((int)pq, (int)(lane() | 3u));
+    // inclusive prefix over the wave's tiles (counted on each tile's last lane)
+    uint32_t pc = part == 3u ? tile_c : 0u, pn = (part == 3u && tile_c) ? 1u : 0u;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
         const uint32_t a = (uint32_t)__shfl_up((int)pc, off);
@@ -181,6 +252,8 @@ __global__ __launch_bounds__(kAllocBlock) void k_alloc(BatchArrays B)
             pn += b;
         }
     }
+    pc = (uint32_t)__shfl((int)pc, (int)(lane() | 3u));
+    pn = (uint32_t)__shfl((int)pn, (int)(lane() | 3u));
     if (lane() == 63) {
         s_wc[wave] = pc;
         s_wn[wave] = pn;
@@ -199,24 +272,38 @@ __global__ __launch_bounds__(kAllocBlock) void k_alloc(BatchArrays B)
         s_base_n = sn ? atomicAdd(&B.ctl->n_nonempty, sn) : 0u;
     }
     __syncthreads();
-    if (c) {
-        uint32_t off = s_base_c + s_wc[wave] + pc - c;
-        for (int sq = 0; sq < H.S; ++sq) {
+    if (tile_c) {
+        // this part's first run: after the wave's earlier tiles and the
+        // tile's earlier parts
+        uint32_t off = s_base_c + s_wc[wave] + (pc - tile_c) + (pq - c);
+        for (int sq = s_lo; sq < s_hi; ++sq) {
             const uint32_t k = (uint32_t)sq * H.gtiles + t;
             const uint32_t ck = B.counts[k];
+            if (!ck) continue;  // runs of empty slots are never read
             B.offsets[k] = off;
             B.cursor[k] = off;
             off += ck;
         }
-        B.nonempty[s_base_n + s_wn[wave] + pn - 1] = t;
-        B.nonempty_map[s_base_n + s_wn[wave] + pn - 1] = (uint32_t)map_of_tile(B, H.nmaps, t);
+        if (part == 0u) {
+            const uint32_t slot = s_base_n + s_wn[wave] + pn - 1u;
+            B.nonempty[slot] = t;
+            B.nonempty_map[slot] = (uint32_t)map_of_tile(B, H.nmaps, t);
+        }
     }
 }
 
+// rdiv(n, d) for 1 <= d <= 2^15 and |n| <= 2^15 d (Eq. (1): n = g w + v,
+// d = w + 1 with |g|, |v| <= tau < 2^15): float64 estimate of
+// floor((2|n| + d) / 2d) from the reciprocal, which is within one of it (the
+// quotient is at most 2^15), then one exact correction each way (every
+// product is an integer below 2^53).
 __device__ __forceinline__ int32_t rdiv_small(int32_t n, int32_t d)
 {
-    const uint32_t a = (uint32_t)(n < 0 ? -n : n);
-    const uint32_t k = (2u * a + (uint32_t)d) / (2u * (uint32_t)d);
+    const double dd = 2.0 * (double)d;
+    const double a = 2.0 * fabs((double)n) + (double)d;
+    double k = floor(a * approx_rcp(dd));
+    k -= k * dd > a ? 1.0 : 0.0;
+    k += __fma_rn(k, dd, dd) <= a ? 1.0 : 0.0;
     return n < 0 ? -(int32_t)k : (int32_t)k;
 }
 
@@ -290,7 +377,9 @@ __device__ __forceinline__ int64_t slot_of_rel(const MapDev &MD, int32_t rx, int
 // G: the candidates of a group's runs are computed together, one LDS key
 // buffer per slot, then each voxel applies the group's scans in submission
 // order. A tile busy in several slots keeps its SDF and weights in LDS.
-__global__ __launch_bounds__(kTileBlock) void k_tile(BatchArrays B)
+// At most 96 VGPRs: five waves per SIMD, the most this kernel holds without
+// spilling.
+__global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_tile(BatchArrays B)
 {
     extern __shared__ uint64_t s_keys[];  // G * tvox keys, then the cached tile: tvox sdf, tvox w
     __shared__ uint32_t s_beg[kMaxSeq], s_cnt[kMaxSeq];
@@ -306,6 +395,7 @@ __global__ __launch_bounds__(kTileBlock) void k_tile(BatchArrays B)
     int16_t *c_w = c_sdf + tvox;
     const uint32_t nne = B.ctl->n_nonempty;
     const uint32_t ez = 1u << H.lt[2], ey = 1u << H.lt[1];
+    const int32_t sh[3] = {H.lt[1] + H.lt[2], H.lt[2], 0};  // LDS index shift per axis
     uint32_t job = blockIdx.x;
     if (job >= nne) return;
     const uint32_t queue = blockIdx.x % kQueues;
@@ -379,53 +469,61 @@ __global__ __launch_bounds__(kTileBlock) void k_tile(BatchArrays B)
                 const uint32_t beg = s_beg[sq0 + r];
                 // the run lies inside the entry buffer unless the fill overflowed
                 if (beg + ee >= H.cap) continue;
-                const uint4 rec = B.entries[beg + ee];
-                const uint32_t i = rec.x;
-                const int32_t q[3] = {(int32_t)rec.y, (int32_t)rec.z, (int32_t)rec.w};
-                RayParams rp;
-                rp.o[0] = s_o[r][0];
-                rp.o[1] = s_o[r][1];
-                rp.o[2] = s_o[r][2];
-                rp.tau = s_tau[r];
+                const uint4 ra = B.entries[beg + ee];
+                const uint4 rb = B.entries2[beg + ee];
+                const uint32_t i = ra.x;
+                const int32_t o[3] = {s_o[r][0], s_o[r][1], s_o[r][2]};
+                const int32_t tau = s_tau[r];
                 Ray R;
                 Walk W;
-                // every binned point has a ray (it was kept when binned)
-                make_ray(q, rp, R);
+                int32_t c[3];
+                ray_of_entry(ra, rb, o, tau, R, c);
                 walk_init(R, W);
+                // resume the walk right after the event that entered the
+                // tile; the box check only moves it further where the tile
+                // is clipped by the window's edge
+                walk_advance(W, c);
                 if (!walk_enter_box(W, blo, bhi)) continue;
+                // the voxels of the walk inside the box are one run
+                BoxWalk V;
+                box_walk_from(W, blo, bhi, sh, V);
                 uint64_t *kb = s_keys + (size_t)r * tvox;
                 uint32_t visits = 0;
-                // the voxels of the walk inside the box are one run
                 do {
-                    if (W.g[0] >= bhi[0] || W.g[1] >= bhi[1] || W.g[2] >= bhi[2] || W.g[0] < blo[0] ||
-                        W.g[1] < blo[1] || W.g[2] < blo[2])
-                        break;
-                    const uint32_t r0 = (uint32_t)(W.g[0] - blo[0]), r1 = (uint32_t)(W.g[1] - blo[1]),
-                                   r2 = (uint32_t)(W.g[2] - blo[2]);
-                    const int32_t sd = voxel_sdf(W.n, R, rp.tau);
-                    const uint32_t lv = (((r0 << H.lt[1]) + r1) << H.lt[2]) + r2;
-                    atomicMin((unsigned long long *)&kb[lv], (unsigned long long)pack_key(sd, i));
+                    const int32_t sd = voxel_sdf(V.n, R, tau);
+                    atomicMin((unsigned long long *)&kb[V.lv], (unsigned long long)pack_key(sd, i));
                     ++visits;
-                } while (walk_next(W));
+                } while (box_walk_next(V));
                 if (H.want_stats && visits) atomicAdd(&s_vis[r], visits);
             }
             __syncthreads();
             if (cached) {
-                // each voxel applies the group's scans in submission order
+                // each voxel applies the group's scans in submission order,
+                // its cached state held in registers across them
                 uint32_t upd[kMaxGroup];
 #pragma unroll
                 for (int r = 0; r < kMaxGroup; ++r) upd[r] = 0;
                 for (uint32_t v = threadIdx.x; v < tvox; v += kTileBlock) {
-                    for (int r = 0; r < ng; ++r) {
+                    int16_t vs = 0, vw = 0;
+                    bool touched = false;
+#pragma unroll
+                    for (int r = 0; r < kMaxGroup; ++r) {
+                        if (r >= ng) break;
                         uint64_t *kp = &s_keys[(size_t)r * tvox + v];
                         const uint64_t key = *kp;
                         if (key == kEmptyKey) continue;
-                        merge_one(c_sdf[v], c_w[v], key, MD.w_max);
-                        *kp = kEmptyKey;
-                        if (H.want_stats) {
-#pragma unroll
-                            for (int rr = 0; rr < kMaxGroup; ++rr) upd[rr] += rr == r;
+                        if (!touched) {
+                            vs = c_sdf[v];
+                            vw = c_w[v];
+                            touched = true;
                         }
+                        merge_one(vs, vw, key, MD.w_max);
+                        *kp = kEmptyKey;
+                        ++upd[r];
+                    }
+                    if (touched) {
+                        c_sdf[v] = vs;
+                        c_w[v] = vw;
                     }
                 }
                 if (H.want_stats)
@@ -540,7 +638,7 @@ hipError_t launch_batch(const BatchArrays &B, const LaunchCaps &caps, hipStream_
     if (ev_start && (e = hipEventRecord(ev_start, stream)) != hipSuccess) return e;
     const uint32_t bins = caps.blocks > 0 ? caps.blocks : 1u;
     hipLaunchKernelGGL(k_bin<false>, dim3(bins), dim3(kBinBlock), 0, stream, B);
-    hipLaunchKernelGGL(k_alloc, dim3((caps.gtiles + kAllocBlock - 1) / kAllocBlock), dim3(kAllocBlock), 0, stream,
+    hipLaunchKernelGGL(k_alloc, dim3((caps.gtiles + kAllocTiles - 1) / kAllocTiles), dim3(kAllocBlock), 0, stream,
                        B);
     hipLaunchKernelGGL(k_bin<true>, dim3(bins), dim3(kBinBlock), 0, stream, B);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -304,7 +304,7 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
             g_cap_ = ng;
         }
     }
-    if ((st = grow(&entries_, &entries_cap_, need_entries * sizeof(uint4), false)) != TSDF_OK) return st;
+    if ((st = grow(&entries_, &entries_cap_, need_entries * 2 * sizeof(uint4), false)) != TSDF_OK) return st;
     if ((st = grow(&valid_, &valid_cap_, cap_blocks * sizeof(uint32_t), false)) != TSDF_OK) return st;
     if ((st = grow(&stats_, &stats_cap_, cap_scans * 4 * sizeof(uint32_t), false)) != TSDF_OK) return st;
 
@@ -349,7 +349,7 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
     hdr->nscans = (int32_t)nscans;
     hdr->gtiles = (uint32_t)gtiles;
     hdr->nblocks = (uint32_t)nblocks;
-    hdr->cap = (uint32_t)std::min<size_t>(entries_cap_ / sizeof(uint4), 0xffffffffu);
+    hdr->cap = (uint32_t)std::min<size_t>(entries_cap_ / (2 * sizeof(uint4)), 0xffffffffu);
     hdr->want_stats = stats ? 1u : 0u;
     memcpy(h + L.maps, md.data(), nmaps * sizeof(MapDev));
     ScanDev *sd = (ScanDev *)(h + L.scans);
@@ -380,10 +380,12 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
     caps.scans = (uint32_t)nscans;
     {
         // LDS of a tile workgroup: G key buffers (8 bytes per voxel) and the
-        // cached tile (4 bytes per voxel); G as large as ~20 KB allows, so
-        // that eight workgroups fit a CU; the persistent grid fills the CUs
+        // cached tile (4 bytes per voxel); G as large as ~32 KB allows, so
+        // that the five workgroups a CU holds (the kernel's register budget
+        // allows five waves per SIMD) fit its 160 KB; the persistent grid
+        // fills the CUs
         const size_t tvox = (size_t)1 << (lt[0] + lt[1] + lt[2]);
-        const int64_t gfit = ((int64_t)(20 * 1024) / (int64_t)tvox - 4) / 8;
+        const int64_t gfit = ((int64_t)(32 * 1024) / (int64_t)tvox - 4) / 8;
         const int32_t G = (int32_t)std::max<int64_t>(1, std::min<int64_t>({gfit, 8, (int64_t)S}));
         hdr->G = G;
         caps.tile_lds = (uint32_t)((8 * (size_t)G + 4) * tvox);
@@ -411,6 +413,7 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
     B.nonempty = (uint32_t *)((char *)arr_ + up(5 * c_cap_ * 4));
     B.nonempty_map = (uint32_t *)((char *)B.nonempty + up(g_cap_ * 4));
     B.entries = (uint4 *)entries_;
+    B.entries2 = B.entries + entries_cap_ / (2 * sizeof(uint4));
     B.valid_part = (uint32_t *)valid_;
     B.scan_stats = (uint32_t *)stats_;
     B.ctl = (BatchCtl *)ctl_;

@@ -82,6 +82,7 @@ struct BatchArrays {
     uint32_t *nonempty;    // [gtiles] tiles with a ray
     uint32_t *nonempty_map; // [gtiles] map slot of each listed tile
     uint4 *entries;        // [cap] (point index, q.x, q.y, q.z), by tile then seq
+    uint4 *entries2;       // [cap] (r, packed band offsets, crossing counts at tile entry)
     uint32_t *valid_part;  // [nblocks] points with a ray per binning block
     uint32_t *scan_stats;  // [nscans * 4] updated, valid, visits, overflow
     BatchCtl *ctl;

@@ -47,13 +47,14 @@ __device__ __forceinline__ bool quantise(float px, float py, float pz, const Ray
     return true;
 }
 
-// floor(sqrt(n)) for n < 2^64 - 2^33: float64 estimate, then exact integer
-// correction (the estimate is within one of the answer).
+// floor(sqrt(n)) for n < 3 * 2^62 (|D|^2 of a ray): float64 estimate, then
+// one exact integer correction each way (the estimate is within one of the
+// answer; (r + 1)^2 < 2^64 for r < 2^32).
 __device__ __forceinline__ uint64_t isqrt_u64(uint64_t n)
 {
     uint64_t r = (uint64_t)sqrt((double)n);
-    while (r * r > n) --r;
-    while ((r + 1) * (r + 1) <= n) ++r;
+    r -= r * r > n ? 1u : 0u;
+    r += (r + 1) * (r + 1) <= n ? 1u : 0u;
     return r;
 }
 
@@ -61,16 +62,17 @@ __device__ __forceinline__ uint64_t isqrt_u64(uint64_t n)
 // afterwards, so its accuracy only decides how many correction steps run.
 __device__ __forceinline__ double approx_rcp(double d) { return __builtin_amdgcn_rcp(d); }
 
-// floor(a / d) for exact integers 0 <= a < 2^53, 0 < d < 2^34, from an
-// estimate a * inv_d (inv_d ~ 1/d): the estimate is capped at cap (callers
-// clamp the quotient there anyway), then corrected until k d <= a < (k+1) d
-// holds (every product is an exact integer below 2^53). The estimate is
-// within one of the quotient, so the loops run at most once.
+// min(floor(a / d), cap) for exact integers 0 <= a < 2^53, 0 < d < 2^34,
+// cap <= 2^17, from an estimate a * inv_d (inv_d ~ 1/d, relative error far
+// below 2^-17): capped at cap (callers clamp the quotient there anyway), the
+// estimate is within one of the answer, so one exact correction each way
+// gives k d <= a < (k + 1) d or k = cap (every product is an exact integer
+// below 2^53).
 __device__ __forceinline__ double floor_div_exact(double a, double d, double inv_d, double cap)
 {
     double k = fmin(floor(a * inv_d), cap);
-    while (k * d > a) k -= 1.0;
-    while (k < cap && __fma_rn(k, d, d) <= a) k += 1.0;  // (k + 1) d <= a
+    k -= k * d > a ? 1.0 : 0.0;
+    k += (k < cap && __fma_rn(k, d, d) <= a) ? 1.0 : 0.0;  // (k + 1) d <= a
     return k;
 }
 
@@ -122,11 +124,17 @@ __device__ __forceinline__ bool make_ray(const int32_t q[3], const RayParams &P,
 }
 
 // Signed distance of the voxel whose centre gives numerator n = (q - c) . D:
-// clamp(rdiv(n, r), -tau, tau).
+// clamp(rdiv(n, r), -tau, tau). The quotient floor((2|n| + r) / 2r) is
+// capped at tau + 1, so its estimate from the reciprocal is within one and a
+// single correction each way makes it exact (compare-and-select, no loop).
 __device__ __forceinline__ int32_t voxel_sdf(double n, const Ray &R, int32_t tau)
 {
-    double k = floor_div_exact(2.0 * fabs(n) + R.r, R.r2, R.inv_r2, (double)tau + 1.0);
-    int32_t s = (int32_t)fmin(k, (double)tau);
+    const double a = 2.0 * fabs(n) + R.r;
+    const double cap = (double)tau + 1.0;
+    double k = fmin(floor(a * R.inv_r2), cap);
+    k -= k * R.r2 > a ? 1.0 : 0.0;
+    k += (k < cap && __fma_rn(k, R.r2, R.r2) <= a) ? 1.0 : 0.0;
+    const int32_t s = (int32_t)fmin(k, (double)tau);
     return n < 0 ? -s : s;
 }
 
@@ -211,19 +219,51 @@ __device__ __forceinline__ bool walk_next(Walk &W)
     return true;
 }
 
+// walk_next that also reports the event it took: its time and its type
+// (0: increasing crossings, 1: decreasing ones).
+__device__ __forceinline__ bool walk_next_event(Walk &W, double &t_ev, int &typ)
+{
+    const double tm = fmin(W.T[0], fmin(W.T[1], W.T[2]));
+    const bool e0 = W.T[0] == tm, e1 = W.T[1] == tm, e2 = W.T[2] == tm;
+    const bool any_up = (e0 && W.step[0] > 0) || (e1 && W.step[1] > 0) || (e2 && W.step[2] > 0);
+    const int dir = any_up ? 1 : -1;
+    if (any_up ? (tm > W.lam) : (tm >= W.lam)) return false;
+    if (e0 && W.step[0] == dir) { W.g[0] += dir; W.T[0] += W.dT[0]; W.n += dir * W.dn[0]; }
+    if (e1 && W.step[1] == dir) { W.g[1] += dir; W.T[1] += W.dT[1]; W.n += dir * W.dn[1]; }
+    if (e2 && W.step[2] == dir) { W.g[2] += dir; W.T[2] += W.dT[2]; W.n += dir * W.dn[2]; }
+    t_ev = tm;
+    typ = any_up ? 0 : 1;
+    return true;
+}
+
 // Crossings of one axis, at times T0 + k dT (k = 0, 1, ...) and of type typ
 // (0: increasing, 1: decreasing), that come at or before the event (Ts, ts)
-// in the walk's order (time, then increasing before decreasing).
+// in the walk's order (time, then increasing before decreasing). The event
+// lies within the segment (Ts <= lam), so the count is at most
+// |L_a| / cell + 1 < 2^7 and the reciprocal's estimate is within one of it.
 __device__ __forceinline__ double crossings_upto(double T0, double dT, int typ, double Ts, int ts)
 {
     if (!(T0 <= Ts)) return 0.0;  // also for an axis that never crosses (T0 = inf)
     const double span = Ts - T0;   // exact: both are integers < 2^53
     double k = floor(span * approx_rcp(dT));
-    while (k * dT > span) k -= 1.0;             // exact: every term is an integer < 2^53
-    while ((k + 1.0) * dT <= span) k += 1.0;
+    k -= k * dT > span ? 1.0 : 0.0;             // exact: every term is an integer < 2^53
+    k += (k + 1.0) * dT <= span ? 1.0 : 0.0;
     double c = k + 1.0;
     if (k * dT == span && typ > ts) c -= 1.0;
     return c;
+}
+
+// Apply c[a] crossings on each axis to a freshly initialised voxel walk (the
+// state right after the event whose crossing counts they are).
+__device__ __forceinline__ void walk_advance(Walk &W, const int32_t c[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double k = (double)c[a];
+        W.g[a] += W.step[a] * c[a];
+        W.T[a] += k * W.dT[a];
+        W.n += (double)W.step[a] * k * W.dn[a];
+    }
 }
 
 // Move a freshly initialised voxel walk to its first voxel inside the box
@@ -271,6 +311,69 @@ __device__ __forceinline__ bool walk_enter_box(Walk &W, const int32_t lo[3], con
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         if (W.g[a] < lo[a] || W.g[a] >= hi[a]) return false;
+    return true;
+}
+
+// The voxel walk restricted to one box, as the tile pass runs it. Event
+// times are re-encoded as T' = 2 T + (1 on a decreasing axis): an increasing
+// crossing then sorts before a decreasing one at the same time, crossings of
+// one kind at one time stay equal (they step together), and "increasing
+// taken for T <= lam, decreasing for T < lam" becomes T' <= 2 lam for both
+// (T integer). Leaving the box is one more event per axis, so the whole
+// stopping rule is one bound: T' <= lim, lim = min(2 lam, first exit - 1).
+// The walk carries the voxel's index in the box (LDS layout, z fastest)
+// instead of its coordinates. Magnitudes: T' < 2^53 (T < 2^52, and a box
+// exit lies at most 64 crossings past the current time).
+struct BoxWalk {
+    double T[3], dT[3];
+    double lim;
+    double n, dn[3];
+    int32_t lv, dlv[3];
+};
+
+// From a voxel walk that walk_enter_box has placed inside [lo, hi); sh[a] is
+// the LDS index shift of axis a.
+__device__ __forceinline__ void box_walk_from(const Walk &W, const int32_t lo[3], const int32_t hi[3],
+                                              const int32_t sh[3], BoxWalk &V)
+{
+    double first_exit = INFINITY;
+    V.lv = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        V.lv += (W.g[a] - lo[a]) << sh[a];
+        if (W.step[a] == 0) {
+            V.T[a] = INFINITY;
+            V.dT[a] = 0.0;
+            V.dn[a] = 0.0;
+            V.dlv[a] = 0;
+            continue;
+        }
+        const bool up = W.step[a] > 0;
+        V.T[a] = 2.0 * W.T[a] + (up ? 0.0 : 1.0);
+        V.dT[a] = 2.0 * W.dT[a];
+        V.dn[a] = up ? W.dn[a] : -W.dn[a];
+        V.dlv[a] = up ? (1 << sh[a]) : -(1 << sh[a]);
+        // crossings until the walk leaves the box on this axis (at least one)
+        const int32_t k = up ? hi[a] - W.g[a] : W.g[a] - lo[a] + 1;
+        first_exit = fmin(first_exit, V.T[a] + (double)(k - 1) * V.dT[a]);
+    }
+    V.lim = fmin(2.0 * W.lam, first_exit - 1.0);
+    V.n = W.n;
+}
+
+// Advance to the next voxel of the box; false when the walk leaves the box
+// or the segment ends.
+__device__ __forceinline__ bool box_walk_next(BoxWalk &V)
+{
+    const double tm = fmin(V.T[0], fmin(V.T[1], V.T[2]));
+    if (tm > V.lim) return false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const bool e = V.T[a] == tm;
+        V.T[a] += e ? V.dT[a] : 0.0;
+        V.n += e ? V.dn[a] : 0.0;
+        V.lv += e ? V.dlv[a] : 0;
+    }
     return true;
 }
 

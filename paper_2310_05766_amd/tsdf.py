@@ -35,7 +35,7 @@ def _points_arg(xyz):
         a = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
         return a.ctypes.data, a.shape[0], _abi.TSDF_PTR_HOST, a
     # torch tensor
-    if xyz.dtype.__str__() != "torch.float32" or not xyz.is_contiguous() or xyz.dim() != 2 or xyz.shape[1] != 3:
+    if str(xyz.dtype) != "torch.float32" or xyz.dim() != 2 or xyz.shape[1] != 3 or not xyz.is_contiguous():
         raise ValueError("device points must be a contiguous float32 tensor of shape (n, 3)")
     if not xyz.is_cuda:
         a = xyz.numpy()
@@ -192,28 +192,32 @@ class TsdfMap:
         return float(ms.value), int(n.value)
 
 
+# numpy view of tsdf_scan_desc (map, xyz, n_points, pose[16])
+_SCAN_DTYPE = np.dtype([("map", np.uint64), ("xyz", np.uint64), ("n", np.int64), ("pose", np.float64, (16,))])
+assert _SCAN_DTYPE.itemsize == C.sizeof(_abi.ScanDesc)
+
+
 def integrate_batch(items, stream=None, stats: bool = False):
     """tsdf_integrate_batch over [(TsdfMap, xyz, pose), ...]; scans sharing a
     map are applied in list order. All points must be of one kind."""
     n = len(items)
-    arr = (_abi.ScanDesc * max(n, 1))()
+    arr = np.zeros(max(n, 1), dtype=_SCAN_DTYPE)
     keep = []
     kinds = set()
     for k, (m, xyz, pose) in enumerate(items):
         ptr, npts, kind, kp = _points_arg(xyz)
         keep.append(kp)
         kinds.add(kind)
-        arr[k].map = m.handle
-        arr[k].xyz = ptr
-        arr[k].n_points = npts
-        M = np.asarray(pose, dtype=np.float64).reshape(16)
-        for j in range(16):
-            arr[k].pose[j] = float(M[j])
+        arr["map"][k] = m.handle
+        arr["xyz"][k] = ptr
+        arr["n"][k] = npts
+        arr["pose"][k] = np.asarray(pose, dtype=np.float64).reshape(16)
     if len(kinds) > 1:
         raise ValueError("a batch takes host points or device points, not both")
     kind = kinds.pop() if kinds else _abi.TSDF_PTR_HOST
     st = (_abi.ScanStats * max(n, 1))() if stats else None
-    check(_abi.lib().tsdf_integrate_batch(arr, n, kind, _stream_handle(stream), st), "tsdf_integrate_batch")
+    check(_abi.lib().tsdf_integrate_batch(arr.ctypes.data_as(C.POINTER(_abi.ScanDesc)), n, kind,
+                                          _stream_handle(stream), st), "tsdf_integrate_batch")
     if stats:
         return [dict(points_in=s.points_in, points_valid=s.points_valid, visits=s.visits,
                      voxels_updated=s.voxels_updated) for s in st[:n]]
