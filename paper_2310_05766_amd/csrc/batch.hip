@@ -62,7 +62,7 @@ __device__ __forceinline__ void ray_of_entry(const uint4 &ra, const uint4 &rb, c
     const bool near = R.r <= (double)tau;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        R.D[a] = (double)((int64_t)R.q[a] - o[a]);
+        R.D[a] = (double)R.q[a] - (double)o[a];  // exact: both below 2^30 in magnitude
         R.E[a] = R.q[a] + off[a];
         R.S[a] = near ? o[a] : R.q[a] - off[a];
     }
@@ -371,6 +371,39 @@ __device__ __forceinline__ int64_t slot_of_rel(const MapDev &MD, int32_t rx, int
     return ((int64_t)sx * MD.dims[1] + sy) * MD.dims[2] + sz;
 }
 
+// Values every lane of a workgroup holds alike, moved to scalar registers
+// (the compiler cannot tell that values read from LDS or memory are uniform,
+// and keeps them, and all derived from them, in vector registers otherwise).
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename T>
+__device__ __forceinline__ T *uniform(T *p)
+{
+    const uint64_t a = (uint64_t)p;
+    return (T *)((uint64_t)uniform((uint32_t)a) | (uint64_t)uniform((uint32_t)(a >> 32)) << 32);
+}
+
+__device__ __forceinline__ MapDev uniform_map(const MapDev &m)
+{
+    MapDev u;
+    u.sdf = uniform(m.sdf);
+    u.w = uniform(m.w);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        u.dims[a] = uniform(m.dims[a]);
+        u.origin[a] = uniform(m.origin[a]);
+        u.ring0[a] = uniform(m.ring0[a]);
+        u.nt[a] = uniform(m.nt[a]);
+    }
+    u.ntot = uniform(m.ntot);
+    u.tile_base = uniform(m.tile_base);
+    u.tau = uniform(m.tau);
+    u.w_max = uniform(m.w_max);
+    u.vec_ok = uniform(m.vec_ok);
+    u.pad = 0;
+    return u;
+}
+
 // Persistent tile pass. Workgroup b first takes busy tile b, then pulls
 // further tiles from queue b % 8 (one queue per XCD keeps same-address
 // atomics spread). Per tile, the busy sequence slots are taken in groups of
@@ -401,8 +434,8 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
     const uint32_t queue = blockIdx.x % kQueues;
     for (uint32_t v = threadIdx.x; v < (uint32_t)G * tvox; v += kTileBlock) s_keys[v] = kEmptyKey;
     while (job < nne) {
-        const uint32_t g = B.nonempty[job];
-        const int32_t mb = (int32_t)B.nonempty_map[job];
+        const uint32_t g = uniform(B.nonempty[job]);
+        const int32_t mb = uniform((int32_t)B.nonempty_map[job]);
         // the tile's runs, one load per sequence slot, all in flight together
         if (threadIdx.x < (uint32_t)H.S) {
             const uint32_t k = threadIdx.x * H.gtiles + g;
@@ -414,7 +447,7 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
         if (threadIdx.x == 0) s_busy = 0;
         __syncthreads();
         if (threadIdx.x < (uint32_t)H.S && s_cnt[threadIdx.x]) atomicAdd(&s_busy, 1u);
-        const MapDev &MD = B.maps[mb];
+        const MapDev MD = uniform_map(B.maps[mb]);
         const uint32_t t = g - MD.tile_base;
         const uint32_t tz = t % (uint32_t)MD.nt[2];
         const uint32_t txy = t / (uint32_t)MD.nt[2];
@@ -428,7 +461,7 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
             bhi[a] = MD.origin[a] + min(t0[a] + (1 << H.lt[a]), MD.dims[a]);
         }
         __syncthreads();
-        const bool cached = s_busy > 1;
+        const bool cached = uniform(s_busy) > 1u;
         if (cached) {
             for (uint32_t v = threadIdx.x; v < tvox; v += kTileBlock) {
                 const int32_t rz = (int32_t)(v & (ez - 1)) + t0[2];
@@ -444,6 +477,7 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
             const int ng = min(G, H.S - sq0);
             uint32_t gsum = 0;
             for (int r = 0; r < ng; ++r) gsum += s_cnt[sq0 + r];
+            gsum = uniform(gsum);
             if (gsum == 0u) continue;  // same value for the whole workgroup
             if (threadIdx.x < (uint32_t)ng) {
                 const int r = (int)threadIdx.x;
@@ -571,7 +605,7 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
         // next tile from this workgroup's queue
         if (threadIdx.x == 0) s_job = gridDim.x + queue + kQueues * atomicAdd(&B.ctl->work[queue], 1u);
         __syncthreads();
-        job = s_job;
+        job = uniform(s_job);
     }
 }
 

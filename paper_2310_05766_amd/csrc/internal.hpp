@@ -23,7 +23,8 @@ namespace tsdf {
 // ---------------------------------------------------------------------------
 
 constexpr int kBinBlock = 256;   // binning threads per block (one ray each)
-constexpr int kMaxEmit = 12;     // tiles per ray listed in LDS before taking positions
+constexpr int kMaxEmit = 6;      // tiles per ray listed in LDS before taking positions (more go
+                                  // straight to their runs)
 constexpr int kHashSlots = 1024; // per-block LDS table that merges (tile, seq) keys
 constexpr int32_t kMaxTileGrid = 65536;
 constexpr int32_t kMaxSeq = 64;  // scans of one map in one batch
