@@ -187,9 +187,13 @@ tsdf_status tsdf_profile_enable(tsdf_map *m, int32_t on);
 
 /* Candidate-buffer tiling of the integration: the window is cut into tiles
  * of 2^log2_tile[a] voxels per axis (each in [2, 6], z at least 3,
- * 2^9..2^13 voxels per tile; a tile's candidate keys live in 8 bytes of LDS per voxel), handled
- * by tile_workgroups persistent workgroups (0: as many as fit the device).
- * The arithmetic, and so every result, is the same for every tiling. */
+ * 2^9..2^12 voxels per tile; a tile's candidate keys live in 8 bytes of LDS
+ * per voxel), handled by tile_workgroups persistent workgroups (0: as many
+ * as fit the device). log2_tile = {0, 0, 0}, the initial setting, lets the
+ * library choose per call (16 x 16 x 8 tiles for tsdf_integrate_scan,
+ * 8 x 8 x 8 for tsdf_integrate_batch, whose tiling is that of its first
+ * scan's map); tsdf_map_get_tiling then reports {0, 0, 0}. The arithmetic,
+ * and so every result, is the same for every tiling. */
 tsdf_status tsdf_map_set_tiling(tsdf_map *m, const int32_t log2_tile[3], int32_t tile_workgroups);
 tsdf_status tsdf_map_get_tiling(const tsdf_map *m, int32_t log2_tile[3], int32_t *tile_workgroups);
 tsdf_status tsdf_profile_read(tsdf_map *m, int32_t kernel, double *total_ms, int64_t *launches);

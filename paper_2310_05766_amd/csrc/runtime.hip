@@ -23,7 +23,7 @@ struct tsdf_map {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
-    int32_t lt[3] = {3, 3, 3};  // integration tiles of 8^3 voxels
+    int32_t lt[3] = {0, 0, 0};  // integration tiling; {0, 0, 0}: chosen per call
     int32_t tile_grid = 0;      // 0: as many workgroups as fit the device
     std::unique_ptr<Engine> engine;  // single-scan integration on the map's stream
     // shift / readback staging
@@ -141,6 +141,18 @@ int64_t nvox_of(const tsdf_map_desc *d) { return (int64_t)d->dims[0] * d->dims[1
 
 // Tiles of 2^lt voxels: every lt in [2, 6], the z edge at least 8 (merge
 // runs), 2^9..2^12 voxels per tile (12 bytes of LDS per voxel).
+// Tilings used while a map has none set: scan-by-scan calls do best with
+// few, large tiles (per-tile fixed costs dominate one scan's work); batches
+// with many scans per tile do best with 8^3 tiles.
+constexpr int32_t kPlainTiling[3] = {4, 4, 3};
+constexpr int32_t kBatchTiling[3] = {3, 3, 3};
+
+const int32_t *tiling_for(const tsdf_map *m, bool batch)
+{
+    if (m->lt[0] != 0) return m->lt;
+    return batch ? kBatchTiling : kPlainTiling;
+}
+
 bool tiling_ok(const int32_t lt[3])
 {
     int sum = 0;
@@ -517,7 +529,7 @@ tsdf_status tsdf_integrate_scan(tsdf_map *m, const float *xyz, int64_t n_points,
     if (m->poisoned) return TSDF_EDEVICE;
     std::vector<MapRef> maps{map_ref(m)};
     std::vector<ScanRef> scans{ScanRef{0, xyz, n_points, kind == TSDF_PTR_HOST, pose}};
-    tsdf_status st = m->engine->run(maps, scans, m->lt, m->tile_grid, stats);
+    tsdf_status st = m->engine->run(maps, scans, tiling_for(m, false), m->tile_grid, stats);
     if (st == TSDF_EDEVICE) m->poisoned = true;
     return st;
 }
@@ -559,7 +571,7 @@ tsdf_status tsdf_integrate_batch(const tsdf_scan_desc *scans, int32_t count, tsd
         eng = slot.get();
     }
     const tsdf_map *first = scans[0].map;
-    tsdf_status st = eng->run(maps, refs, first->lt, first->tile_grid, stats);
+    tsdf_status st = eng->run(maps, refs, tiling_for(first, true), first->tile_grid, stats);
     if (st == TSDF_EDEVICE)
         for (int32_t k = 0; k < count; ++k) scans[k].map->poisoned = true;
     return st;
@@ -836,8 +848,9 @@ const char *tsdf_kernel_name(int32_t kernel)
 
 tsdf_status tsdf_map_set_tiling(tsdf_map *m, const int32_t log2_tile[3], int32_t tile_workgroups)
 {
-    if (!m || !log2_tile || !tiling_ok(log2_tile) || tile_workgroups < 0 || tile_workgroups > kMaxTileGrid)
-        return TSDF_EINVAL;
+    if (!m || !log2_tile || tile_workgroups < 0 || tile_workgroups > kMaxTileGrid) return TSDF_EINVAL;
+    const bool automatic = log2_tile[0] == 0 && log2_tile[1] == 0 && log2_tile[2] == 0;
+    if (!automatic && !tiling_ok(log2_tile)) return TSDF_EINVAL;
     Guard g(m);
     if (!g.ok) return TSDF_EBUSY;
     if (m->poisoned) return TSDF_EDEVICE;

@@ -124,9 +124,13 @@ def test_every_tiling_gives_the_same_map(lt):
 def test_invalid_tilings_rejected():
     from paper_2310_05766_amd import TsdfError
     gm = gpu_map((32, 32, 32), (-16, -16, -16), 0.05, 3072, 64)
-    for lt in [(1, 4, 4), (3, 3, 2), (7, 3, 3), (2, 2, 3), (5, 5, 5)]:
+    assert gm.get_tiling()[0] == (0, 0, 0)  # chosen per call until set
+    for lt in [(1, 4, 4), (3, 3, 2), (7, 3, 3), (2, 2, 3), (5, 5, 5), (0, 3, 3)]:
         with pytest.raises(TsdfError):
             gm.set_tiling(lt)
+    gm.set_tiling((4, 4, 4))
+    gm.set_tiling((0, 0, 0))
+    assert gm.get_tiling()[0] == (0, 0, 0)
     gm.close()
 
 
