@@ -12,6 +12,9 @@ Prints ONE JSON line. Extra legs (all outside the timed region):
     the roofline of the dominant kernel;
   * synchronous per-scan latency (p50 / p99);
   * the ring-buffer shift of a 512 x 512 x 128 window (host-link bound);
+  * 256 uneven scans into 16 maps: one launch, launches of 16, one call per
+    scan;
+  * the serving loop on 48 sessions (real-time and compressed replays);
   * the CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -141,6 +144,71 @@ def shift_leg(torch, TsdfMap, synth):
             "host_link_GBps": moved / t / 1e9}
 
 
+def uneven_batch_leg(torch, synth, reps: int = 3):
+    """Config 4: 256 scans of uneven shapes (16x512 .. 128x2048) into 16 maps
+    of 256^3 at 8 cm, scan i into map i mod 16. Three forms on the same
+    resident points, each rep starting from fresh maps: one launch for all
+    256 scans (16 per map, in order), 16 launches of one scan per map, and
+    one tsdf_integrate_scan per scan. The autotuner picks the batch tiling
+    on the first 16 scans."""
+    from paper_2310_05766_amd.autotune import autotune
+    from paper_2310_05766_amd.tsdf import TsdfMap, integrate_batch
+
+    shapes = synth.config4_shapes()
+    scans = [synth.config4_scan(i, shapes[i]) for i in range(256)]
+    spec = synth.MapSpec((256, 256, 256), (-128, -128, -128), 0.08, 5120, 64)
+    dev = [torch.from_numpy(sc.xyz).to("cuda") for sc in scans]
+    poses = [sc.pose for sc in scans]
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    best = autotune(spec, list(zip(dev[:16], poses[:16])), mode="batch", reps=2, use_cache=False)
+    lt = tuple(best["lt"])
+
+    def fresh(tiling):
+        ms = [TsdfMap.from_spec(spec, stream=st) for _ in range(16)]
+        if tiling:
+            for m in ms:
+                m.set_tiling(tiling, best["workgroups"])
+        return ms
+
+    def timed(form, tiling):
+        out = []
+        for _ in range(reps):
+            ms = fresh(tiling)
+            items = [(ms[i % 16], dev[i], poses[i]) for i in range(256)]
+            st.synchronize()
+            t0 = time.perf_counter()
+            if form == "all":
+                integrate_batch(items, stream=st)
+            elif form == "per16":
+                for b in range(0, 256, 16):
+                    integrate_batch(items[b:b + 16], stream=st)
+            else:
+                for m, x, p in items:
+                    m.integrate(x, p)
+            st.synchronize()
+            out.append(time.perf_counter() - t0)
+            for m in ms:
+                m.close()
+        return min(out)
+
+    ms = fresh(lt)
+    stats = integrate_batch([(ms[i % 16], dev[i], poses[i]) for i in range(256)], stream=st, stats=True)
+    st.synchronize()
+    for m in ms:
+        m.close()
+    upd = sum(x["voxels_updated"] for x in stats)
+    timed("all", lt)  # warm every engine and graph shape once
+    timed("per16", lt)
+    timed("plain", None)
+    t_all, t_16, t_plain = timed("all", lt), timed("per16", lt), timed("plain", None)
+    return {"scans": 256, "points": int(sum(d.shape[0] for d in dev)), "voxel_updates": upd,
+            "autotuned": {"lt": list(lt), "workgroups": best["workgroups"]},
+            "one_launch": {"scans_per_s": 256 / t_all, "voxel_updates_per_s": upd / t_all, "ms": 1e3 * t_all},
+            "launch_per_16": {"scans_per_s": 256 / t_16, "voxel_updates_per_s": upd / t_16, "ms": 1e3 * t_16},
+            "plain": {"scans_per_s": 256 / t_plain, "voxel_updates_per_s": upd / t_plain, "ms": 1e3 * t_plain}}
+
+
 def serving_leg(torch, synth, seconds: float, speedup: float, pool: int = 8):
     """Config-5 serving: 48 sessions (maps 256^3 / 384^3 / 512x512x256 at
     6.4 cm), 16x1024 scans arriving Poisson at 10 Hz per session. A real-time
@@ -202,6 +270,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-shift", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the 256 uneven scans leg")
     ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--profile-only", action="store_true", help="warmup + timed steps only (for rocprofv3)")
     ap.add_argument("--plain-only", action="store_true", help="with --profile-only: per-scan calls only")
@@ -343,6 +412,10 @@ def main():
     gm.close()
 
     shift = None if args.no_shift else shift_leg(torch, TsdfMap, synth)
+    uneven = None
+    if not args.no_uneven:
+        log("uneven batches (config 4)")
+        uneven = uneven_batch_leg(torch, synth)
     serving = None
     if not args.no_serving:
         log("serving (config 5)")
@@ -404,6 +477,7 @@ def main():
             "achieved_GBps": B_batch / (kt["launch"]["avg_us"] * 1e-6) / 1e9,
         },
         "shift": shift,
+        "uneven_batches": uneven,
         "serving": serving,
         "cpu_baseline": cpu,
         "sources_sha256": sources_digest(),
