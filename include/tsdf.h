@@ -185,6 +185,28 @@ typedef enum {
 
 tsdf_status tsdf_profile_enable(tsdf_map *m, int32_t on);
 
+/* Vertical interpolation between scan lines (Sec. VI, Eq. (3), Eq. (4)),
+ * for the map's following scans: every band voxel also gives its value to
+ * the voxels along the interpolation vector int = d x (d x up) (d: the ray,
+ * up: the sensor's z axis), up to h = delta_z * len above and below the ray,
+ * where len is the voxel's distance along the ray and
+ * delta_z = tan(vfov_deg / hlines, in radians) (Eq. (3)). In fixed point:
+ * d = rdiv(1024 D, r), up in 1/1024 units, delta_z in 1/2^20 units,
+ * h = min(rdiv(delta_z len, 2^20), 65535), e = rdiv(h int, |int|); the
+ * filled voxels of band voxel centre c are the floor-set of [c - e, c + e],
+ * each receiving the band voxel's key; the per-scan minimum decides as for
+ * the band. Rays with r >= 2^30 are not filled. vfov_deg = 0 turns it off;
+ * vfov_deg / hlines must be below 45 degrees (else TSDF_EINVAL). The first
+ * call that turns it on allocates an 8-byte key per voxel of the window
+ * (TSDF_ENOMEM if that fails). Interpolating maps take their own
+ * integration path (one thread per ray, 64-bit atomicMin on the key
+ * volume); in tsdf_integrate_batch their scans run one by one, in order, on
+ * their map's stream, ordered after the batch stream's earlier work and
+ * before its later work. */
+tsdf_status tsdf_map_set_interpolation(tsdf_map *m, double vfov_deg, int32_t hlines);
+/* delta_z in 1/2^20 units, 0 when off. */
+tsdf_status tsdf_map_get_interpolation(const tsdf_map *m, int64_t *delta_q20);
+
 /* Candidate-buffer tiling of the integration: the window is cut into tiles
  * of 2^log2_tile[a] voxels per axis (each in [2, 6], z at least 3,
  * 2^9..2^12 voxels per tile; a tile's candidate keys live in 8 bytes of LDS

@@ -72,6 +72,14 @@ def lib():
         L.or_window.argtypes = [C.c_void_p, C.POINTER(C.c_int16), C.POINTER(C.c_int16), i32p]
         L.or_store_chunks.restype = C.c_int64
         L.or_store_chunks.argtypes = [C.c_void_p]
+        L.or_interp_delta.restype = C.c_int64
+        L.or_interp_delta.argtypes = [C.c_double, C.c_int32]
+        L.or_up_vector.restype = None
+        L.or_up_vector.argtypes = [C.POINTER(C.c_double), i64p]
+        L.or_fill_offset.restype = None
+        L.or_fill_offset.argtypes = [i64p, i64p, i64p, C.c_uint64, i64p, i64p, C.c_int64, i64p]
+        L.or_set_interpolation.restype = C.c_int
+        L.or_set_interpolation.argtypes = [C.c_void_p, C.c_int64]
         L.or_recentre.restype = C.c_int
         L.or_recentre.argtypes = [i32p, i32p, C.c_double, C.POINTER(C.c_double), C.c_int64, C.c_int32,
                                   C.c_int, i32p]
@@ -147,6 +155,28 @@ def key(s: int, i: int) -> int:
     return int(lib().or_key(int(s), int(i)))
 
 
+def interp_delta(vfov_deg: float, hlines: int) -> int:
+    """Eq. (3) as a fixed-point integer (1/2^20 units)."""
+    return int(lib().or_interp_delta(float(vfov_deg), int(hlines)))
+
+
+def up_vector(pose):
+    M = np.ascontiguousarray(np.asarray(pose, dtype=np.float64).reshape(16))
+    U = _i64([0, 0, 0])
+    lib().or_up_vector(_p(M, C.c_double), _p(U, C.c_int64))
+    return tuple(int(v) for v in U)
+
+
+def fill_offset(q, o, D, r, U, g, dq):
+    """Offset e of the fill segment [c - e, c + e] of band voxel g."""
+    e = _i64([0, 0, 0])
+    args = [_i64(v) for v in (q, o, D)]
+    Ua, ga = _i64(U), _i64(g)
+    lib().or_fill_offset(*[_p(a, C.c_int64) for a in args], int(r), _p(Ua, C.c_int64), _p(ga, C.c_int64), int(dq),
+                         _p(e, C.c_int64))
+    return tuple(int(v) for v in e)
+
+
 def recentre(dims, origin, voxel_size, pose, radius_u, chunk=64, force=False):
     """(shift_due, new_origin) of the local-map recentre rule."""
     out = np.zeros(3, dtype=np.int32)
@@ -188,6 +218,14 @@ class OracleMap:
             self.close()
         except Exception:
             pass
+
+    def set_interpolation(self, vfov_deg: float = 0.0, hlines: int = 0, dq: int | None = None):
+        """Vertical interpolation between scan lines for the following scans
+        (vfov in degrees over hlines scan lines; vfov 0 turns it off)."""
+        d = interp_delta(vfov_deg, hlines) if dq is None else int(dq)
+        if lib().or_set_interpolation(self._m, d) != 0:
+            raise ValueError("interpolation angle out of range")
+        return d
 
     def integrate(self, xyz, pose) -> dict:
         x = np.ascontiguousarray(np.asarray(xyz, dtype=np.float32).reshape(-1, 3))

@@ -259,6 +259,67 @@ uint64_t or_key(int64_t s, uint64_t i)
 }
 
 /* ------------------------------------------------------------------ */
+/* vertical interpolation between scan lines (Sec. VI, Eq. (3), Eq. (4)) */
+/* ------------------------------------------------------------------ */
+
+/* Eq. (3): delta_z = tan(rad(vfov / hlines)), vfov in degrees (reading: the
+ * angle between neighbouring scan lines, converted to radians), as a fixed-
+ * point integer in 1/2^20 units; 0 for an invalid sensor description or an
+ * angle of 45 degrees or more (delta_z >= 1). */
+int64_t or_interp_delta(double vfov_deg, int32_t hlines)
+{
+    if (!(vfov_deg > 0.0) || !isfinite(vfov_deg) || hlines < 1) return 0;
+    const double step = vfov_deg / (double)hlines;
+    if (!(step < 45.0)) return 0;
+    return (int64_t)llrint(tan(step * (M_PI / 180.0)) * 1048576.0);
+}
+
+/* The sensor's up vector (its z axis in the world frame, column 2 of the
+ * pose's rotation) in 1/1024 units, rounded half to even. */
+void or_up_vector(const double M[16], int64_t U[3])
+{
+    for (int a = 0; a < 3; ++a) U[a] = (int64_t)llrint(M[4 * a + 2] * 1024.0);
+}
+
+/* The fill offset e of one band voxel g of a ray (q, D, r): the paper fills
+ * the voxels along the interpolation vector int = d x (d x up), scaled to
+ * h = delta_z * len (Eq. (4)), above and below the ray. Readings, all in
+ * exact integers:
+ *   d  = rdiv(1024 D, r)                 (the ray direction, |d| ~ 1024)
+ *   int = d x (d x U)                    (U: up vector in 1/1024 units)
+ *   len = rdiv((c - o) . D, r)           (distance of the voxel centre c
+ *                                          along the ray, fixed point)
+ *   h  = min(rdiv(dq len, 2^20), 65535) if len > 0, else 0
+ *   e  = rdiv(h int, |int|), |int| = isqrt(int . int); e = 0 if |int| = 0
+ * The fill height is capped at 64 voxels (65535 in 1/1024 units), and rays
+ * of r >= 2^30 get no fill (e = 0). The filled voxels are the floor-set of
+ * the closed segment [c - e, c + e]. */
+void or_fill_offset(const int64_t q[3], const int64_t o[3], const int64_t D[3], uint64_t r, const int64_t U[3],
+                    const int64_t g[3], int64_t dq, int64_t e[3])
+{
+    e[0] = e[1] = e[2] = 0;
+    if (dq <= 0 || r == 0 || r >= ((uint64_t)1 << 30)) return;
+    const int64_t rr = (int64_t)r;
+    int64_t d[3], w[3], v[3];
+    for (int a = 0; a < 3; ++a) d[a] = or_rdiv(1024 * D[a], rr);
+    w[0] = d[1] * U[2] - d[2] * U[1];
+    w[1] = d[2] * U[0] - d[0] * U[2];
+    w[2] = d[0] * U[1] - d[1] * U[0];
+    v[0] = d[1] * w[2] - d[2] * w[1];
+    v[1] = d[2] * w[0] - d[0] * w[2];
+    v[2] = d[0] * w[1] - d[1] * w[0];
+    const int64_t nv = (int64_t)or_isqrt((uint64_t)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+    if (nv == 0) return;
+    int64_t proj = 0; /* (c - o) . D */
+    for (int a = 0; a < 3; ++a) proj += (1024 * g[a] + 512 - o[a]) * D[a];
+    const int64_t len = or_rdiv(proj, rr);
+    if (len <= 0) return;
+    int64_t h = or_rdiv(dq * len, (int64_t)1 << 20);
+    if (h > 65535) h = 65535;
+    for (int a = 0; a < 3; ++a) e[a] = or_rdiv(h * v[a], nv);
+}
+
+/* ------------------------------------------------------------------ */
 /* map: window over the global volume G, plus the store of what left it */
 /* ------------------------------------------------------------------ */
 
@@ -272,6 +333,7 @@ typedef struct omap_s {
     int32_t origin[3];
     double voxel_size, scale;
     int64_t tau_u, w_max;
+    int64_t interp_dq; /* vertical interpolation: delta_z in 1/2^20 units, 0 = off */
     int64_t nvox;
     int16_t *sdf, *w; /* resident window, slot = floor_mod(g, dims) */
     uint64_t *K;      /* per-scan volume V as candidate keys, EMPTY = none */
@@ -437,6 +499,10 @@ static int build_volume(omap *m, const float *xyz, int64_t n, const double M[16]
     int64_t cap = 4096;
     int64_t *vox = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)cap);
     if (!vox) return OR_ENOMEM;
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)cap);
+    if (!fill) { free(vox); return OR_ENOMEM; }
+    int64_t U[3];
+    or_up_vector(M, U);
     *valid = 0;
     *visits = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -446,19 +512,39 @@ static int build_volume(omap *m, const float *xyz, int64_t n, const double M[16]
         if (!or_band(q, o, m->tau_u, D, &r, S, E)) continue;
         (*valid)++;
         int nv = or_segment_voxels(S, E, vox, (int)cap);
-        if (nv < 0) { free(vox); return OR_ENOMEM; }
+        if (nv < 0) { free(vox); free(fill); return OR_ENOMEM; }
         for (int k = 0; k < nv; ++k) {
             int64_t *g = &vox[3 * k];
-            if (!in_window(m->origin, m->dims, g)) continue;
-            (*visits)++;
             int64_t s = or_voxel_sdf(q, D, r, g, m->tau_u);
             uint64_t key = or_key(s, (uint64_t)i);
-            int64_t sl = slot_of(m, g);
-            if (m->K[sl] == KEY_EMPTY) m->touched[m->ntouched++] = sl;
-            if (key < m->K[sl]) m->K[sl] = key;
+            /* the voxels this band voxel gives its value to: itself, or with
+             * vertical interpolation the floor-set of [c - e, c + e] (a band
+             * voxel outside the window may still fill voxels inside it) */
+            int nf = 1;
+            const int64_t *fv = g;
+            if (m->interp_dq > 0) {
+                int64_t e[3], A[3], Bv[3];
+                or_fill_offset(q, o, D, r, U, g, m->interp_dq, e);
+                for (int a = 0; a < 3; ++a) {
+                    A[a] = 1024 * g[a] + 512 - e[a];
+                    Bv[a] = 1024 * g[a] + 512 + e[a];
+                }
+                nf = or_segment_voxels(A, Bv, fill, (int)cap);
+                if (nf < 0) { free(vox); free(fill); return OR_ENOMEM; }
+                fv = fill;
+            }
+            for (int f = 0; f < nf; ++f) {
+                const int64_t *gf = &fv[3 * f];
+                if (!in_window(m->origin, m->dims, gf)) continue;
+                (*visits)++;
+                int64_t sl = slot_of(m, gf);
+                if (m->K[sl] == KEY_EMPTY) m->touched[m->ntouched++] = sl;
+                if (key < m->K[sl]) m->K[sl] = key;
+            }
         }
     }
     free(vox);
+    free(fill);
     return OR_OK;
 }
 
@@ -484,6 +570,15 @@ static int64_t merge_volume(omap *m)
     }
     m->ntouched = 0;
     return U;
+}
+
+/* Vertical interpolation for the following scans: dq = delta_z in 1/2^20
+ * units (or_interp_delta), 0 to turn it off. */
+int or_set_interpolation(omap *m, int64_t dq)
+{
+    if (!m || dq < 0 || dq >= ((int64_t)1 << 20)) return OR_EINVAL;
+    m->interp_dq = dq;
+    return OR_OK;
 }
 
 /* stats[4] = points_in, points_valid, visits, voxels_updated */

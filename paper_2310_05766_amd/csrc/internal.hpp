@@ -109,6 +109,21 @@ hipError_t launch_batch(const BatchArrays &B, const LaunchCaps &caps, hipStream_
                         hipEvent_t ev_binned, hipEvent_t ev_tiles);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
 
+// One scan with vertical interpolation between scan lines (interp.hip).
+struct InterpScan {
+    RayParams rp;
+    const float *xyz;  // device points
+    int64_t n;
+    int64_t dq;        // delta_z of Eq. (3) in 1/2^20 units
+    int64_t up[3];     // the sensor's up vector in 1/1024 units
+    int32_t origin[3], dims[3];
+    int16_t *sdf, *w;
+    int32_t w_max;
+    unsigned long long *keys;      // [nx*ny*nz] per-scan keys, all EMPTY between scans
+    unsigned long long *counters;  // valid points, visits, voxels updated (added to)
+};
+hipError_t launch_interp(const InterpScan &P, int64_t nvox, hipStream_t stream);
+
 // ---------------------------------------------------------------------------
 // Host-side store of 64^3-voxel chunks that left the window.
 // ---------------------------------------------------------------------------

@@ -1,0 +1,159 @@
+// Vertical interpolation between scan lines (FeatSense, arXiv 2310.05766,
+// Sec. VI, Eq. (3) and Eq. (4)): every band voxel of a ray also gives its
+// value to the voxels along the interpolation vector int = d x (d x up),
+// up to the height h = delta_z * len above and below the ray, where len is
+// the voxel's distance along the ray. The filled voxels of one band voxel
+// are the exact floor-set of the segment [c - e, c + e] around its centre c,
+// with e = h int / |int| in fixed point; each receives the band voxel's key,
+// and the per-scan minimum over all keys (band and fill, all rays) decides.
+//
+// A fill reaches across tiles, so this form does not use the tiled engine:
+// one thread walks one ray's band and each band voxel's fill segment and
+// resolves keys with 64-bit atomicMin on a key volume over the window (8
+// bytes per voxel, all EMPTY between scans); a second kernel merges every
+// key set (Eq. (1), Eq. (2)) and empties it again.
+//
+// Integer ranges (all exact): d = rdiv(1024 D, r) has |d| <= 1026, the up
+// vector U is in 1/1024 units, so |int| < 2^31 and int . int < 2^62; a fill
+// applies to rays of r < 2^30 (|D|^2 < 2^62); h is capped at 65535 (64
+// voxels), so a fill segment spans |2 e_a| < 2^17 per axis, the range the
+// exact walk is built for.
+#include "internal.hpp"
+
+namespace tsdf {
+
+namespace {
+
+constexpr int kInterpBlock = 256;
+
+// rdiv(n, d) for d > 0: to nearest, ties away from zero (64-bit integers).
+__device__ __forceinline__ int64_t rdiv64(int64_t n, int64_t d)
+{
+    const uint64_t a = (uint64_t)(n < 0 ? -n : n);
+    const uint64_t k = (2 * a + (uint64_t)d) / (2 * (uint64_t)d);
+    return n < 0 ? -(int64_t)k : (int64_t)k;
+}
+
+__device__ __forceinline__ int64_t floor_mod64(int64_t a, int64_t b)
+{
+    const int64_t m = a % b;
+    return m < 0 ? m + b : m;
+}
+
+// Eq. (1) with one unit of weight, Eq. (2) (|g w + v| <= tau (w + 1)).
+__device__ __forceinline__ void merge_key(int16_t &sdf, int16_t &w, uint64_t key, int32_t w_max)
+{
+    const int64_t v = (int16_t)(uint16_t)(key & 0xffffu);
+    const int64_t gw = w, gv = sdf;
+    sdf = (int16_t)rdiv64(gv * gw + v, gw + 1);
+    w = (int16_t)(gw + 1 < w_max ? gw + 1 : w_max);
+}
+
+__device__ __forceinline__ void block_add(uint64_t v, unsigned long long *dst)
+{
+    __shared__ unsigned long long s_sum;
+    if (threadIdx.x == 0) s_sum = 0;
+    __syncthreads();
+    if (v) atomicAdd(&s_sum, (unsigned long long)v);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_sum) atomicAdd(dst, s_sum);
+}
+
+__global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
+{
+    const int64_t i = (int64_t)blockIdx.x * kInterpBlock + threadIdx.x;
+    uint64_t valid = 0, visits = 0;
+    int32_t q[3];
+    Ray R;
+    if (i < P.n && quantise(P.xyz[3 * i], P.xyz[3 * i + 1], P.xyz[3 * i + 2], P.rp, q) && make_ray(q, P.rp, R)) {
+        valid = 1;
+        const int64_t rr = (int64_t)R.r;
+        int64_t Di[3], v[3] = {0, 0, 0}, nv = 0, dd = 0;
+        for (int a = 0; a < 3; ++a) Di[a] = (int64_t)R.D[a];
+        const bool fills = P.dq > 0 && rr < ((int64_t)1 << 30);
+        if (fills) {
+            int64_t d[3], w[3];
+            for (int a = 0; a < 3; ++a) {
+                d[a] = rdiv64(1024 * Di[a], rr);
+                dd += Di[a] * Di[a];
+            }
+            w[0] = d[1] * P.up[2] - d[2] * P.up[1];
+            w[1] = d[2] * P.up[0] - d[0] * P.up[2];
+            w[2] = d[0] * P.up[1] - d[1] * P.up[0];
+            v[0] = d[1] * w[2] - d[2] * w[1];
+            v[1] = d[2] * w[0] - d[0] * w[2];
+            v[2] = d[0] * w[1] - d[1] * w[0];
+            nv = (int64_t)isqrt_u64((uint64_t)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+        }
+        Walk W;
+        walk_init(R, W);
+        do {
+            const int32_t s = voxel_sdf(W.n, R, P.rp.tau);
+            const unsigned long long key = pack_key(s, (uint32_t)i);
+            // the fill segment of this band voxel: [c - e, c + e]
+            int64_t e[3] = {0, 0, 0};
+            if (fills && nv > 0) {
+                // (c - o) . D = (q - o) . D - (q - c) . D, the walk's n
+                const int64_t len = rdiv64(dd - (int64_t)W.n, rr);
+                if (len > 0) {
+                    int64_t h = rdiv64(P.dq * len, (int64_t)1 << 20);
+                    h = h < 65535 ? h : 65535;
+                    for (int a = 0; a < 3; ++a) e[a] = rdiv64(h * v[a], nv);
+                }
+            }
+            Ray F;  // a segment only: the fill walk needs no distances
+            for (int a = 0; a < 3; ++a) {
+                const int32_t c = 1024 * W.g[a] + 512;
+                F.S[a] = c - (int32_t)e[a];
+                F.E[a] = c + (int32_t)e[a];
+                F.q[a] = 0;
+                F.D[a] = 0.0;
+            }
+            Walk FW;
+            walk_init(F, FW);
+            do {
+                bool inside = true;
+                for (int a = 0; a < 3; ++a)
+                    inside = inside && FW.g[a] >= P.origin[a] && FW.g[a] < P.origin[a] + P.dims[a];
+                if (inside) {
+                    const int64_t slot =
+                        (floor_mod64(FW.g[0], P.dims[0]) * P.dims[1] + floor_mod64(FW.g[1], P.dims[1])) * P.dims[2] +
+                        floor_mod64(FW.g[2], P.dims[2]);
+                    atomicMin(&P.keys[slot], key);
+                    ++visits;
+                }
+            } while (walk_next(FW));
+        } while (walk_next(W));
+    }
+    block_add(valid, &P.counters[0]);
+    block_add(visits, &P.counters[1]);
+}
+
+__global__ __launch_bounds__(256) void k_interp_merge(InterpScan P, int64_t nvox)
+{
+    uint64_t updated = 0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nvox; j += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long key = P.keys[j];
+        if (key == kEmptyKey) continue;
+        merge_key(P.sdf[j], P.w[j], key, P.w_max);
+        P.keys[j] = kEmptyKey;
+        ++updated;
+    }
+    block_add(updated, &P.counters[2]);
+}
+
+}  // namespace
+
+hipError_t launch_interp(const InterpScan &P, int64_t nvox, hipStream_t stream)
+{
+    if (P.n > 0) {
+        const int64_t blocks = (P.n + kInterpBlock - 1) / kInterpBlock;
+        hipLaunchKernelGGL(k_interp_scan, dim3((uint32_t)blocks), dim3(kInterpBlock), 0, stream, P);
+    }
+    int64_t mblocks = (nvox + 255) / 256;
+    if (mblocks > 8192) mblocks = 8192;
+    hipLaunchKernelGGL(k_interp_merge, dim3((uint32_t)(mblocks > 0 ? mblocks : 1)), dim3(256), 0, stream, P, nvox);
+    return hipGetLastError();
+}
+
+}  // namespace tsdf

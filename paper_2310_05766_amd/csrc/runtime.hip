@@ -26,6 +26,13 @@ struct tsdf_map {
     int32_t lt[3] = {0, 0, 0};  // integration tiling; {0, 0, 0}: chosen per call
     int32_t tile_grid = 0;      // 0: as many workgroups as fit the device
     std::unique_ptr<Engine> engine;  // single-scan integration on the map's stream
+    // vertical interpolation between scan lines (its own path, interp.hip)
+    int64_t interp_dq = 0;                     // delta_z of Eq. (3), 1/2^20 units; 0: off
+    unsigned long long *interp_keys = nullptr;  // [nvox], EMPTY between scans
+    unsigned long long *interp_ctr = nullptr;   // device counters (3)
+    unsigned long long *interp_ctr_host = nullptr;
+    float *interp_pts = nullptr;                // device copy of host points
+    int64_t interp_pts_cap = 0;                 // points
     // shift / readback staging
     int16_t *stage_dev = nullptr;  // [2][stage_cap]
     int16_t *stage_host = nullptr;
@@ -224,6 +231,10 @@ void release(tsdf_map *m)
     if (m->stage_host) (void)hipHostFree(m->stage_host);
     if (m->boxes_dev) (void)hipFree(m->boxes_dev);
     if (m->boxes_host) (void)hipHostFree(m->boxes_host);
+    if (m->interp_keys) (void)hipFree(m->interp_keys);
+    if (m->interp_ctr) (void)hipFree(m->interp_ctr);
+    if (m->interp_ctr_host) (void)hipHostFree(m->interp_ctr_host);
+    if (m->interp_pts) (void)hipFree(m->interp_pts);
     prof_clear(m);
     for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
     if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
@@ -519,6 +530,99 @@ tsdf_status tsdf_map_destroy(tsdf_map *m)
     return TSDF_OK;
 }
 
+// One scan through the interpolating path, on the map's stream.
+static tsdf_status integrate_interp(tsdf_map *m, const float *xyz, int64_t n, bool host, const double pose[16],
+                             tsdf_scan_stats *stats)
+{
+    for (int k = 0; k < 12; ++k)
+        if (!std::isfinite(pose[k])) return TSDF_EINVAL;
+    InterpScan P;
+    for (int k = 0; k < 12; ++k) P.rp.M[k] = pose[k];
+    P.rp.scale = m->scale;
+    for (int a = 0; a < 3; ++a) {
+        const double o = nearbyint(pose[4 * a + 3] * m->scale);
+        if (!(fabs(o) < 1073741824.0)) return TSDF_EINVAL;
+        P.rp.o[a] = (int32_t)o;
+        P.up[a] = (int64_t)nearbyint(pose[4 * a + 2] * 1024.0);
+        P.origin[a] = m->d.origin[a];
+        P.dims[a] = m->d.dims[a];
+    }
+    P.rp.tau = m->d.tau_q10;
+    P.n = n;
+    P.dq = m->interp_dq;
+    P.sdf = m->sdf;
+    P.w = m->w;
+    P.w_max = m->d.w_max;
+    P.keys = m->interp_keys;
+    P.counters = m->interp_ctr;
+    P.xyz = xyz;
+    if (host && n > 0) {
+        if (n > m->interp_pts_cap) {
+            HIPCHK(m, hipStreamSynchronize(m->stream));
+            if (m->interp_pts) HIPCHK(m, hipFree(m->interp_pts));
+            m->interp_pts = nullptr;
+            m->interp_pts_cap = 0;
+            if (hipMalloc(&m->interp_pts, (size_t)n * 3 * sizeof(float)) != hipSuccess) return TSDF_ENOMEM;
+            m->interp_pts_cap = n;
+        }
+        // synchronous from pageable memory: the caller may reuse xyz at once
+        HIPCHK(m, hipMemcpyAsync(m->interp_pts, xyz, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice,
+                                 m->stream));
+        HIPCHK(m, hipStreamSynchronize(m->stream));
+        P.xyz = m->interp_pts;
+    }
+    HIPCHK(m, launch_fill_u32((uint32_t *)m->interp_ctr, 6, 0u, m->stream));
+    HIPCHK(m, launch_interp(P, m->nvox, m->stream));
+    if (stats) {
+        HIPCHK(m, hipMemcpyAsync(m->interp_ctr_host, m->interp_ctr, 3 * sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, m->stream));
+        HIPCHK(m, hipStreamSynchronize(m->stream));
+        stats->points_in = n;
+        stats->points_valid = (int64_t)m->interp_ctr_host[0];
+        stats->visits = (int64_t)m->interp_ctr_host[1];
+        stats->voxels_updated = (int64_t)m->interp_ctr_host[2];
+    }
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_map_set_interpolation(tsdf_map *m, double vfov_deg, int32_t hlines)
+{
+    if (!m) return TSDF_EINVAL;
+    int64_t dq = 0;
+    if (vfov_deg != 0.0) {
+        // Eq. (3): delta_z = tan(rad(vfov / hlines)), below 1
+        if (!(vfov_deg > 0.0) || !std::isfinite(vfov_deg) || hlines < 1) return TSDF_EINVAL;
+        const double step = vfov_deg / (double)hlines;
+        if (!(step < 45.0)) return TSDF_EINVAL;
+        dq = (int64_t)llrint(tan(step * (M_PI / 180.0)) * 1048576.0);
+    }
+    Guard g(m);
+    if (!g.ok) return TSDF_EBUSY;
+    if (m->poisoned) return TSDF_EDEVICE;
+    if (dq > 0 && !m->interp_keys) {
+        if (hipMalloc(&m->interp_keys, (size_t)m->nvox * sizeof(unsigned long long)) != hipSuccess) {
+            m->interp_keys = nullptr;
+            return TSDF_ENOMEM;
+        }
+        if (hipMalloc(&m->interp_ctr, 4 * sizeof(unsigned long long)) != hipSuccess ||
+            hipHostMalloc(&m->interp_ctr_host, 4 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+            (void)hipFree(m->interp_keys);
+            m->interp_keys = nullptr;
+            return TSDF_ENOMEM;
+        }
+        HIPCHK(m, launch_fill_u32((uint32_t *)m->interp_keys, m->nvox * 2, 0xffffffffu, m->stream));
+    }
+    m->interp_dq = dq;
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_map_get_interpolation(const tsdf_map *m, int64_t *delta_q20)
+{
+    if (!m || !delta_q20) return TSDF_EINVAL;
+    *delta_q20 = m->interp_dq;
+    return TSDF_OK;
+}
+
 tsdf_status tsdf_integrate_scan(tsdf_map *m, const float *xyz, int64_t n_points, tsdf_ptr_kind kind,
                                 const double pose[16], tsdf_scan_stats *stats)
 {
@@ -527,6 +631,7 @@ tsdf_status tsdf_integrate_scan(tsdf_map *m, const float *xyz, int64_t n_points,
     Guard g(m);
     if (!g.ok) return TSDF_EBUSY;
     if (m->poisoned) return TSDF_EDEVICE;
+    if (m->interp_dq > 0) return integrate_interp(m, xyz, n_points, kind == TSDF_PTR_HOST, pose, stats);
     std::vector<MapRef> maps{map_ref(m)};
     std::vector<ScanRef> scans{ScanRef{0, xyz, n_points, kind == TSDF_PTR_HOST, pose}};
     tsdf_status st = m->engine->run(maps, scans, tiling_for(m, false), m->tile_grid, stats);
@@ -540,6 +645,49 @@ tsdf_status tsdf_integrate_batch(const tsdf_scan_desc *scans, int32_t count, tsd
     if (count < 0 || (count > 0 && !scans)) return TSDF_EINVAL;
     if (kind != TSDF_PTR_HOST && kind != TSDF_PTR_DEVICE) return TSDF_EINVAL;
     if (count == 0) return TSDF_OK;
+    // Scans of maps with vertical interpolation take their own path, one by
+    // one in order on their map's stream, between events on the batch
+    // stream; the others go through the batched engine as one batch. (Maps
+    // are independent, so the two groups may run in either order.)
+    bool any_interp = false;
+    for (int32_t k = 0; k < count; ++k) {
+        if (!scans[k].map) return TSDF_EINVAL;
+        any_interp = any_interp || scans[k].map->interp_dq > 0;
+    }
+    if (any_interp) {
+        hipStream_t bs = hip_stream ? (hipStream_t)hip_stream : scans[0].map->stream;
+        std::vector<tsdf_scan_desc> rest;
+        std::vector<int32_t> rest_at;
+        for (int32_t k = 0; k < count; ++k) {
+            tsdf_map *m = scans[k].map;
+            if (m->interp_dq <= 0) {
+                rest.push_back(scans[k]);
+                rest_at.push_back(k);
+                continue;
+            }
+            Guard g(m);
+            if (!g.ok) return TSDF_EBUSY;
+            if (m->poisoned) return TSDF_EDEVICE;
+            hipEvent_t before = take_event(m), after = take_event(m);
+            if (!before || !after) return fail_device(m);
+            HIPCHK(m, hipEventRecord(before, bs));
+            HIPCHK(m, hipStreamWaitEvent(m->stream, before, 0));
+            tsdf_status st = integrate_interp(m, scans[k].xyz, scans[k].n_points, kind == TSDF_PTR_HOST,
+                                              scans[k].pose, stats ? &stats[k] : nullptr);
+            if (st != TSDF_OK) return st;
+            HIPCHK(m, hipEventRecord(after, m->stream));
+            HIPCHK(m, hipStreamWaitEvent(bs, after, 0));
+            m->ev_pool.push_back(before);
+            m->ev_pool.push_back(after);
+        }
+        if (rest.empty()) return TSDF_OK;
+        std::vector<tsdf_scan_stats> rst(stats ? rest.size() : 0);
+        tsdf_status st = tsdf_integrate_batch(rest.data(), (int32_t)rest.size(), kind, (void *)bs,
+                                              stats ? rst.data() : nullptr);
+        if (st == TSDF_OK && stats)
+            for (size_t j = 0; j < rest.size(); ++j) stats[rest_at[j]] = rst[j];
+        return st;
+    }
     std::vector<MapRef> maps;
     std::vector<ScanRef> refs;
     std::unordered_map<const tsdf_map *, int32_t> idx;

@@ -169,6 +169,19 @@ class TsdfMap:
     def synchronize(self):
         check(_abi.lib().tsdf_map_synchronize(self._h), "tsdf_map_synchronize")
 
+    def set_interpolation(self, vfov_deg: float = 0.0, hlines: int = 0):
+        """Vertical interpolation between scan lines for the following scans
+        (vfov in degrees over hlines scan lines; vfov 0 turns it off).
+        Returns delta_z in 1/2^20 units."""
+        check(_abi.lib().tsdf_map_set_interpolation(self._h, float(vfov_deg), int(hlines)),
+              "tsdf_map_set_interpolation")
+        return self.get_interpolation()
+
+    def get_interpolation(self) -> int:
+        d = C.c_int64()
+        check(_abi.lib().tsdf_map_get_interpolation(self._h, C.byref(d)), "tsdf_map_get_interpolation")
+        return int(d.value)
+
     def set_tiling(self, log2_tile, workgroups: int = 0):
         """Candidate-buffer tiling (2^log2_tile voxels per axis); results do not depend on it."""
         lt = (C.c_int32 * 3)(*[int(v) for v in log2_tile])

@@ -1,0 +1,132 @@
+"""GPU parity of vertical interpolation between scan lines (Sec. VI,
+Eq. (3), Eq. (4)): maps, per-scan counts and the switch between the
+interpolating and the tiled paths, bit-exact with the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_map(dims, origin, vs, tau, wmax):
+    from paper_2310_05766_amd.tsdf import TsdfMap
+    return TsdfMap(dims, origin, vs, tau, wmax)
+
+
+def same(gm, om, dims):
+    o = gm.origin
+    hi = tuple(o[a] + dims[a] for a in range(3))
+    g = gm.readback(o, hi)
+    r = om.readback(o, hi)
+    return np.array_equal(g[0], r[0]) and np.array_equal(g[1], r[1])
+
+
+def test_config1_interpolated_bit_exact():
+    w = synth.config1()
+    spec, sc = w.maps[0], w.scans[0]
+    say("config1 with interpolation (30 deg over 16 lines)")
+    om = oracle.OracleMap.from_spec(spec)
+    gm = gpu_map(spec.dims, spec.origin, spec.voxel_size, spec.tau_u, spec.w_max)
+    assert gm.set_interpolation(30.0, 16) == om.set_interpolation(30.0, 16) > 0
+    poses = [sc.pose] + [synth.fuzz_pose((61, k), 0.5) for k in range(3)]
+    for k, p in enumerate(poses):
+        gst = gm.integrate(sc.xyz, p, stats=True)
+        ost = om.integrate(sc.xyz, p)
+        assert gst == ost, (k, gst, ost)
+    assert same(gm, om, spec.dims)
+    gm.close()
+    om.close()
+
+
+def test_config2_scans_interpolated_bit_exact():
+    w = synth.config2(3)
+    spec = w.maps[0]
+    say("config2 first scans with interpolation (45 deg over 128 lines)")
+    om = oracle.OracleMap.from_spec(spec)
+    gm = gpu_map(spec.dims, spec.origin, spec.voxel_size, spec.tau_u, spec.w_max)
+    gm.set_interpolation(45.0, 128)
+    om.set_interpolation(45.0, 128)
+    for k, sc in enumerate(w.scans):
+        gst = gm.integrate(sc.xyz, sc.pose, stats=True)
+        ost = om.integrate(sc.xyz, sc.pose)
+        assert gst == ost, (k, gst, ost)
+    assert same(gm, om, spec.dims)
+    gm.close()
+    om.close()
+
+
+FUZZ = [((24, 24, 24), (-12, -12, -12), 0.1, 3072, 64, 40.0, 4),
+        ((33, 17, 29), (-16, -9, -14), 0.07, 2048, 5, 60.0, 4),
+        ((16, 40, 12), (-8, -20, -6), 0.12, 5120, 64, 22.5, 3)]
+
+
+@pytest.mark.parametrize("case", range(len(FUZZ)))
+def test_fuzz_steep_interpolation(case):
+    """Large angles between scan lines: long fills reaching across the
+    window's edges, odd window shapes, NaN slots and index ties."""
+    dims, origin, vs, tau, wmax, vfov, lines = FUZZ[case]
+    om = oracle.OracleMap(dims, origin, vs, tau, wmax)
+    gm = gpu_map(dims, origin, vs, tau, wmax)
+    om.set_interpolation(vfov, lines)
+    gm.set_interpolation(vfov, lines)
+    for k in range(4):
+        xyz = synth.fuzz_scan((case, k, 62), 2500, extent_m=1.2, nan_frac=0.05,
+                              grid_snap=0.1 if k == 1 else None)
+        xyz[10:14] = xyz[3]
+        pose = synth.fuzz_pose((case, k, 63), 0.4)
+        assert gm.integrate(xyz, pose, stats=True) == om.integrate(xyz, pose), k
+    assert same(gm, om, dims)
+    gm.close()
+    om.close()
+
+
+def test_switching_paths_and_batches():
+    """Interpolation on, off and on again on one map, while a second map
+    without it shares the same batches; device points; the batch's per-scan
+    counts in submission order."""
+    import torch
+    from paper_2310_05766_amd.tsdf import integrate_batch
+    spec = ((32, 32, 32), (-16, -16, -16), 0.08, 3072, 64)
+    g1, g2 = gpu_map(*spec), gpu_map(*spec)
+    o1, o2 = oracle.OracleMap(*spec), oracle.OracleMap(*spec)
+    for step, mode in enumerate(("on", "off", "on")):
+        if mode == "on":
+            g1.set_interpolation(30.0, 8)
+            o1.set_interpolation(30.0, 8)
+        else:
+            g1.set_interpolation(0.0, 0)
+            o1.set_interpolation(0.0, 0)
+        items, refs = [], []
+        for k in range(5):
+            xyz = synth.fuzz_scan((64, step, k), 1800, extent_m=1.0, nan_frac=0.03)
+            pose = synth.fuzz_pose((65, step, k), 0.3)
+            gm, om = (g1, o1) if k % 2 == 0 else (g2, o2)
+            items.append((gm, torch.from_numpy(xyz).to("cuda"), pose))
+            refs.append(om.integrate(xyz, pose))
+        say("batch, interpolation", mode)
+        assert integrate_batch(items, stats=True) == refs
+        assert same(g1, o1, spec[0]) and same(g2, o2, spec[0])
+    for m in (g1, g2, o1, o2):
+        m.close()
+
+
+def test_interpolation_arguments():
+    from paper_2310_05766_amd import TsdfError
+    gm = gpu_map((16, 16, 16), (-8, -8, -8), 0.1, 3072, 64)
+    assert gm.get_interpolation() == 0
+    for vfov, lines in [(-1.0, 16), (30.0, 0), (90.0, 2), (float("nan"), 4)]:
+        with pytest.raises(TsdfError):
+            gm.set_interpolation(vfov, lines)
+    assert gm.get_interpolation() == 0
+    assert gm.set_interpolation(45.0, 128) == oracle.interp_delta(45.0, 128)
+    assert gm.set_interpolation(0.0, 0) == 0
+    gm.close()

@@ -360,3 +360,212 @@ def test_stats_counts():
     # point 2 coincides with the sensor (D = 0): skipped; point 3 repeats point 0
     assert st == dict(points_in=4, points_valid=2, visits=14, voxels_updated=7)
     m.close()
+
+
+# -- vertical interpolation between scan lines (Sec. VI, Eq. (3), Eq. (4)) ----
+
+def _round_half_away(x: Fraction) -> int:
+    a = abs(x)
+    k = int(a + Fraction(1, 2))  # floor(a + 1/2)
+    return k if x >= 0 else -k
+
+
+def test_interp_delta_eq3():
+    # Eq. (3) with degrees converted to radians, in 1/2^20 units (half even)
+    for vfov, lines in [(45.0, 128), (30.0, 16), (90.0, 64), (22.5, 32), (40.0, 4)]:
+        want = round(math.tan(math.radians(vfov / lines)) * 2 ** 20)
+        assert oracle.interp_delta(vfov, lines) == want
+    for vfov, lines in [(0.0, 16), (-5.0, 16), (30.0, 0), (90.0, 2), (200.0, 3)]:
+        assert oracle.interp_delta(vfov, lines) == 0  # invalid, or angle >= 45 deg
+
+
+def test_fill_offset_axis_rays_closed_form():
+    """Identity pose (up = +z): a ray along x or y is filled straight down and
+    up, e = (0, 0, -h) with h = delta_z * (distance of the voxel centre along
+    the ray), rounded half away from zero and capped at 64 voxels."""
+    U = oracle.up_vector(np.eye(4))
+    assert U == (0, 0, 1024)
+    dq = oracle.interp_delta(45.0, 128)
+    for axis, sign in [(0, 1), (0, -1), (1, 1), (1, -1)]:
+        o = [512, -1536, 2560]
+        for dist in (7 * 1024 + 300, 200 * 1024 + 5, 9000 * 1024 + 77):
+            q = list(o)
+            q[axis] += sign * dist
+            D = [q[a] - o[a] for a in range(3)]
+            r = abs(D[axis])
+            for k in (-3, 0, 2):  # band voxels around the point
+                g = [(o[a]) // 1024 for a in range(3)]
+                g[axis] = (q[axis] // 1024) + k
+                c = 1024 * g[axis] + 512
+                length = sign * (c - o[axis])  # projection onto the ray, exact here
+                h = min(_round_half_away(Fraction(dq * length, 2 ** 20)), 65535) if length > 0 else 0
+                e = oracle.fill_offset(q, o, D, r, U, g, dq)
+                assert e == (0, 0, -h), (axis, sign, dist, k, e, h)
+    # a vertical ray has no interpolation direction
+    e = oracle.fill_offset((0, 0, 50 * 1024), (0, 0, 0), (0, 0, 50 * 1024), 50 * 1024, U, (0, 0, 49), dq)
+    assert e == (0, 0, 0)
+
+
+def test_fill_offset_geometry_random():
+    """Properties of e for random rays and poses: perpendicular to the ray,
+    in the plane of the ray and the sensor's up vector, pointing against up,
+    of length h up to rounding."""
+    g = np.random.default_rng(41)
+    dq = oracle.interp_delta(30.0, 16)
+    checked = 0
+    for it in range(400):
+        M = synth.fuzz_pose((41, it), max_t=2.0)
+        U = oracle.up_vector(M)
+        o = [int(v) for v in g.integers(-50000, 50000, size=3)]
+        D = [int(v) for v in g.integers(-400000, 400000, size=3)]
+        q = [o[a] + D[a] for a in range(3)]
+        r = math.isqrt(sum(v * v for v in D))
+        if r == 0:
+            continue
+        k = [q[a] // 1024 for a in range(3)]
+        e = oracle.fill_offset(q, o, D, r, U, k, dq)
+        c = [1024 * k[a] + 512 for a in range(3)]
+        length = Fraction(sum((c[a] - o[a]) * D[a] for a in range(3)), r)
+        h = min(float(length) * dq / 2 ** 20, 65535)
+        ne = math.sqrt(sum(v * v for v in e))
+        cross = [D[1] * U[2] - D[2] * U[1], D[2] * U[0] - D[0] * U[2], D[0] * U[1] - D[1] * U[0]]
+        nc = math.sqrt(sum(v * v for v in cross))
+        if nc < 1e-3 * r * 1024:  # ray nearly along up: direction ill-defined
+            continue
+        assert abs(ne - h) <= 2.0 + 4e-3 * h, (ne, h)
+        if ne > 50:
+            dot_d = sum(e[a] * D[a] for a in range(3)) / (ne * r)
+            dot_plane = sum(e[a] * cross[a] for a in range(3)) / (ne * nc)
+            dot_up = sum(e[a] * U[a] for a in range(3))
+            assert abs(dot_d) < 4e-3 + 2.0 / ne, dot_d
+            assert abs(dot_plane) < 4e-3 + 2.0 / ne, dot_plane
+            assert dot_up <= 0
+            checked += 1
+    assert checked > 200
+
+
+def _axis_ray_map(dq, tau=3072):
+    m = oracle.OracleMap((40, 8, 24), (0, 0, -12), 1.0, tau, 64)
+    m.set_interpolation(dq=dq)
+    return m
+
+
+def test_interp_volume_axis_ray_closed_form():
+    """One ray along +x from (0.5, 4.5, 0.5) voxels to x = 30.2: band voxels
+    get the plane profile, each fills its column from floor((c_z - h)/1024)
+    to floor((c_z + h)/1024), and a voxel reached from several band voxels
+    keeps the smallest |s| (one ray: no index ties to break)."""
+    dq = oracle.interp_delta(40.0, 4)  # tan(10 deg): fills of a few voxels
+    tau = 3072
+    m = _axis_ray_map(dq, tau)
+    pose = np.eye(4)
+    pose[:3, 3] = [0.5, 4.5, 0.5]
+    X = 30.2
+    xyz = np.array([[X - 0.5, 0.0, 0.0]], dtype=np.float32)
+    keys = m.volume(xyz, pose)
+    # closed form
+    ox = 512
+    qx = int(round(float(np.float32(X - 0.5)) * 1024)) + 512
+    expect = {}
+    for gx in range((qx - tau) // 1024, (qx + tau) // 1024 + 1):
+        cx = 1024 * gx + 512
+        s = max(-tau, min(tau, qx - cx))
+        h = min(_round_half_away(Fraction(dq * (cx - ox), 2 ** 20)), 65535)
+        cz = 512
+        for gz in range((cz - h) // 1024, (cz + h) // 1024 + 1):
+            key = (abs(s) << 48) | (s & 0xFFFF)
+            if not (-12 <= gz < 12):
+                continue
+            expect[(gx, 4, gz)] = min(expect.get((gx, 4, gz), 1 << 64), key)
+    assert len(expect) > 20
+    for gx in range(40):
+        for gy in range(8):
+            for gz in range(-12, 12):
+                kk = int(keys[gx, gy, gz % 24])
+                assert kk == expect.get((gx, gy, gz), 0xFFFFFFFFFFFFFFFF), (gx, gy, gz)
+    m.close()
+
+
+def _interp_case(seed):
+    g = np.random.default_rng(seed)
+    xyz = g.uniform(-3.0, 3.0, size=(30, 3)).astype(np.float32)
+    xyz[5] = np.nan
+    xyz[7:9] = xyz[0]  # index ties
+    return xyz, synth.fuzz_pose((seed, 3), max_t=1.0)
+
+
+@pytest.mark.parametrize("seed", [51, 52, 53])
+def test_interp_volume_vs_brute_force(seed):
+    """The interpolated volume over a 16^3 window against a brute-force
+    assembly: band from the pinned band function, band voxels and fill voxels
+    from the exact-rational floor-set of each segment (not the oracle's
+    walk), fill offsets from the pinned fill_offset, minimum over keys."""
+    vs, tau = 0.5, 1536
+    scale = 1024.0 / vs
+    dims, origin = (16, 16, 16), (-8, -8, -8)
+    dq = oracle.interp_delta(60.0, 4)  # tan(15 deg)
+    xyz, M = _interp_case(seed)
+    m = oracle.OracleMap(dims, origin, vs, tau, 64)
+    m.set_interpolation(dq=dq)
+    keys = m.volume(xyz, M)
+    o = oracle.quantise_origin(M, scale)
+    U = oracle.up_vector(M)
+    best = {}
+    for i, p in enumerate(xyz):
+        q = oracle.quantise_point(p, M, scale)
+        if q is None:
+            continue
+        b = oracle.band(q, o, tau)
+        if b is None:
+            continue
+        D, r, S, E = b
+        q, D, S, E = ([int(v) for v in a] for a in (q, D, S, E))
+        o = [int(v) for v in o]
+        blo = [min(S[a], E[a]) // 1024 for a in range(3)]
+        bhi = [max(S[a], E[a]) // 1024 + 1 for a in range(3)]
+        band_vox = brute.segment_voxels_brute(S, E, blo, bhi)
+        for gb in band_vox:
+            s = oracle.voxel_sdf(q, D, r, gb, tau)
+            key = (abs(s) << 48) | (i << 16) | (s & 0xFFFF)
+            e = oracle.fill_offset(q, o, D, r, U, gb, dq)
+            c = [1024 * gb[a] + 512 for a in range(3)]
+            A = [c[a] - e[a] for a in range(3)]
+            Bv = [c[a] + e[a] for a in range(3)]
+            lo = [min(A[a], Bv[a]) // 1024 for a in range(3)]
+            hi = [max(A[a], Bv[a]) // 1024 + 1 for a in range(3)]
+            for gf in brute.segment_voxels_brute(A, Bv, lo, hi):
+                if all(origin[a] <= gf[a] < origin[a] + dims[a] for a in range(3)):
+                    best[gf] = min(best.get(gf, 1 << 64), key)
+    hits = 0
+    for gx in range(origin[0], origin[0] + dims[0]):
+        for gy in range(origin[1], origin[1] + dims[1]):
+            for gz in range(origin[2], origin[2] + dims[2]):
+                kk = int(keys[gx % 16, gy % 16, gz % 16])
+                assert kk == best.get((gx, gy, gz), 0xFFFFFFFFFFFFFFFF), (gx, gy, gz)
+                hits += kk != 0xFFFFFFFFFFFFFFFF
+    assert hits > 100
+    m.close()
+
+
+def test_interp_invariants_room_scan():
+    """Turning interpolation off gives the plain volume; with it on, every
+    voxel the plain volume holds is still held, with a key no larger, and
+    more voxels are reached."""
+    w = synth.config1()
+    sc = w.scans[0]
+    spec = w.maps[0]
+    sub = sc.xyz[::8]
+    plain = oracle.OracleMap.from_spec(spec)
+    kp = plain.volume(sub, sc.pose)
+    off = oracle.OracleMap.from_spec(spec)
+    off.set_interpolation(30.0, 16)
+    off.set_interpolation(0.0, 0)
+    assert np.array_equal(off.volume(sub, sc.pose), kp)
+    on = oracle.OracleMap.from_spec(spec)
+    on.set_interpolation(30.0, 16)
+    ki = on.volume(sub, sc.pose)
+    held = kp != np.uint64(0xFFFFFFFFFFFFFFFF)
+    assert np.all(ki[held] <= kp[held])
+    assert int((ki != np.uint64(0xFFFFFFFFFFFFFFFF)).sum()) > int(held.sum())
+    for m in (plain, off, on):
+        m.close()
