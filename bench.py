@@ -14,6 +14,7 @@ Prints ONE JSON line. Extra legs (all outside the timed region):
   * the ring-buffer shift of a 512 x 512 x 128 window (host-link bound);
   * 256 uneven scans into 16 maps: one launch, launches of 16, one call per
     scan;
+  * vertical interpolation between scan lines on 10 of the same scans;
   * the serving loop on 48 sessions (real-time and compressed replays);
   * the CPU oracle on a bounded sample of the same workload.
 """
@@ -144,6 +145,42 @@ def shift_leg(torch, TsdfMap, synth):
             "host_link_GBps": moved / t / 1e9}
 
 
+def interp_leg(torch, synth, TsdfMap, n_scans: int = 10, reps: int = 5):
+    """Vertical interpolation between scan lines (45 deg over 128 lines, the
+    OS1-128's) on the first scans of the config-2 sequence, one call per
+    scan on the map's stream, timed with HIP events on that stream."""
+    w = synth.config2(n_scans)
+    spec = w.maps[0]
+    dev = [torch.from_numpy(sc.xyz).to("cuda") for sc in w.scans]
+    st = torch.cuda.Stream()
+    m = TsdfMap.from_spec(spec, stream=st)
+    dq = m.set_interpolation(45.0, 128)
+    stats = [m.integrate(x, sc.pose, stats=True) for x, sc in zip(dev, w.scans)]
+    upd = sum(x["voxels_updated"] for x in stats)
+    visits = sum(x["visits"] for x in stats)
+    pts = sum(x["points_in"] for x in stats)
+    for x, sc in zip(dev, w.scans):  # warm
+        m.integrate(x, sc.pose)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    st.synchronize()
+    e0.record(st)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for x, sc in zip(dev, w.scans):
+            m.integrate(x, sc.pose)
+    e1.record(st)
+    st.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = e0.elapsed_time(e1) * 1e-3
+    m.close()
+    n = reps * n_scans
+    B = 12.0 * pts + 128.0 * n_scans + 8.0 * upd  # per pass over the scans
+    return {"scans": n_scans, "delta_z_q20": dq, "visits_per_scan": visits / n_scans,
+            "voxel_updates_per_scan": upd / n_scans, "scans_per_s": n / wall,
+            "voxel_updates_per_s": upd * reps / wall, "gpu_ms_per_scan": 1e3 * gpu_s / n,
+            "algorithmic_GBps": B * reps / gpu_s / 1e9, "hbm_frac": B * reps / gpu_s / 1e9 / HBM_PEAK_GBS}
+
+
 def uneven_batch_leg(torch, synth, reps: int = 3):
     """Config 4: 256 scans of uneven shapes (16x512 .. 128x2048) into 16 maps
     of 256^3 at 8 cm, scan i into map i mod 16. Three forms on the same
@@ -271,6 +308,9 @@ def main():
     ap.add_argument("--no-shift", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the 256 uneven scans leg")
+    ap.add_argument("--no-interp", action="store_true", help="skip the vertical interpolation leg")
+    ap.add_argument("--interp-only", action="store_true",
+                    help="with --profile-only: the interpolating path on 10 config-2 scans only")
     ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--profile-only", action="store_true", help="warmup + timed steps only (for rocprofv3)")
     ap.add_argument("--plain-only", action="store_true", help="with --profile-only: per-scan calls only")
@@ -301,6 +341,9 @@ def main():
     from paper_2310_05766_amd.tsdf import TsdfMap, integrate_batch
 
     torch.cuda.set_device(0)
+    if args.profile_only and args.interp_only:
+        log(f"profile-only: interpolation {interp_leg(torch, synth, TsdfMap, reps=max(1, args.steps // 4))}")
+        return
     log("generating config-2 scans")
     w = synth.config2(args.scans)
     spec = w.maps[0]
@@ -412,6 +455,10 @@ def main():
     gm.close()
 
     shift = None if args.no_shift else shift_leg(torch, TsdfMap, synth)
+    interp = None
+    if not args.no_interp:
+        log("vertical interpolation")
+        interp = interp_leg(torch, synth, TsdfMap)
     uneven = None
     if not args.no_uneven:
         log("uneven batches (config 4)")
@@ -478,6 +525,7 @@ def main():
         },
         "shift": shift,
         "uneven_batches": uneven,
+        "interpolation": interp,
         "serving": serving,
         "cpu_baseline": cpu,
         "sources_sha256": sources_digest(),

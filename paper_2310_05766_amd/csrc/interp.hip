@@ -10,8 +10,10 @@
 // A fill reaches across tiles, so this form does not use the tiled engine:
 // one thread walks one ray's band and each band voxel's fill segment and
 // resolves keys with 64-bit atomicMin on a key volume over the window (8
-// bytes per voxel, all EMPTY between scans); a second kernel merges every
-// key set (Eq. (1), Eq. (2)) and empties it again.
+// bytes per voxel, all EMPTY between scans) and marks the key's run of 64
+// slots as touched (one byte per run, a plain store); a second kernel, one
+// wave per run, merges the keys of touched runs (Eq. (1), Eq. (2)) and
+// empties them again.
 //
 // Integer ranges (all exact): d = rdiv(1024 D, r) has |d| <= 1026, the up
 // vector U is in 1/1024 units, so |int| < 2^31 and int . int < 2^62; a fill
@@ -120,6 +122,7 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
                         (floor_mod64(FW.g[0], P.dims[0]) * P.dims[1] + floor_mod64(FW.g[1], P.dims[1])) * P.dims[2] +
                         floor_mod64(FW.g[2], P.dims[2]);
                     atomicMin(&P.keys[slot], key);
+                    P.touched[slot >> 6] = 1;
                     ++visits;
                 }
             } while (walk_next(FW));
@@ -129,15 +132,27 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
     block_add(visits, &P.counters[1]);
 }
 
+// One wave per run of 64 slots; runs never touched this scan are skipped
+// after reading their byte.
 __global__ __launch_bounds__(256) void k_interp_merge(InterpScan P, int64_t nvox)
 {
     uint64_t updated = 0;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nvox; j += (int64_t)gridDim.x * blockDim.x) {
-        const unsigned long long key = P.keys[j];
-        if (key == kEmptyKey) continue;
-        merge_key(P.sdf[j], P.w[j], key, P.w_max);
-        P.keys[j] = kEmptyKey;
-        ++updated;
+    const int64_t nruns = (nvox + 63) / 64;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t waves = (int64_t)gridDim.x * blockDim.x / 64;
+    const int lane = (int)(threadIdx.x & 63u);
+    for (int64_t b = wave; b < nruns; b += waves) {
+        if (!P.touched[b]) continue;  // the same for the whole wave
+        const int64_t j = b * 64 + lane;
+        if (j < nvox) {
+            const unsigned long long key = P.keys[j];
+            if (key != kEmptyKey) {
+                merge_key(P.sdf[j], P.w[j], key, P.w_max);
+                P.keys[j] = kEmptyKey;
+                ++updated;
+            }
+        }
+        if (lane == 0) P.touched[b] = 0;
     }
     block_add(updated, &P.counters[2]);
 }
@@ -150,7 +165,7 @@ hipError_t launch_interp(const InterpScan &P, int64_t nvox, hipStream_t stream)
         const int64_t blocks = (P.n + kInterpBlock - 1) / kInterpBlock;
         hipLaunchKernelGGL(k_interp_scan, dim3((uint32_t)blocks), dim3(kInterpBlock), 0, stream, P);
     }
-    int64_t mblocks = (nvox + 255) / 256;
+    int64_t mblocks = (nvox + 255) / 256;  // four runs of 64 slots per block
     if (mblocks > 8192) mblocks = 8192;
     hipLaunchKernelGGL(k_interp_merge, dim3((uint32_t)(mblocks > 0 ? mblocks : 1)), dim3(256), 0, stream, P, nvox);
     return hipGetLastError();

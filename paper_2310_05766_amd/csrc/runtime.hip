@@ -29,6 +29,7 @@ struct tsdf_map {
     // vertical interpolation between scan lines (its own path, interp.hip)
     int64_t interp_dq = 0;                     // delta_z of Eq. (3), 1/2^20 units; 0: off
     unsigned long long *interp_keys = nullptr;  // [nvox], EMPTY between scans
+    uint8_t *interp_touched = nullptr;          // [ceil(nvox / 64)], 0 between scans
     unsigned long long *interp_ctr = nullptr;   // device counters (3)
     unsigned long long *interp_ctr_host = nullptr;
     float *interp_pts = nullptr;                // device copy of host points
@@ -232,6 +233,7 @@ void release(tsdf_map *m)
     if (m->boxes_dev) (void)hipFree(m->boxes_dev);
     if (m->boxes_host) (void)hipHostFree(m->boxes_host);
     if (m->interp_keys) (void)hipFree(m->interp_keys);
+    if (m->interp_touched) (void)hipFree(m->interp_touched);
     if (m->interp_ctr) (void)hipFree(m->interp_ctr);
     if (m->interp_ctr_host) (void)hipHostFree(m->interp_ctr_host);
     if (m->interp_pts) (void)hipFree(m->interp_pts);
@@ -554,6 +556,7 @@ static tsdf_status integrate_interp(tsdf_map *m, const float *xyz, int64_t n, bo
     P.w = m->w;
     P.w_max = m->d.w_max;
     P.keys = m->interp_keys;
+    P.touched = m->interp_touched;
     P.counters = m->interp_ctr;
     P.xyz = xyz;
     if (host && n > 0) {
@@ -604,13 +607,17 @@ tsdf_status tsdf_map_set_interpolation(tsdf_map *m, double vfov_deg, int32_t hli
             m->interp_keys = nullptr;
             return TSDF_ENOMEM;
         }
+        const int64_t runs = (m->nvox + 63) / 64;
+        const size_t touched_bytes = (size_t)((runs + 3) / 4 * 4);
         if (hipMalloc(&m->interp_ctr, 4 * sizeof(unsigned long long)) != hipSuccess ||
-            hipHostMalloc(&m->interp_ctr_host, 4 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+            hipHostMalloc(&m->interp_ctr_host, 4 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
+            hipMalloc(&m->interp_touched, touched_bytes) != hipSuccess) {
             (void)hipFree(m->interp_keys);
             m->interp_keys = nullptr;
             return TSDF_ENOMEM;
         }
         HIPCHK(m, launch_fill_u32((uint32_t *)m->interp_keys, m->nvox * 2, 0xffffffffu, m->stream));
+        HIPCHK(m, launch_fill_u32((uint32_t *)m->interp_touched, (int64_t)(touched_bytes / 4), 0u, m->stream));
     }
     m->interp_dq = dq;
     return TSDF_OK;
