@@ -323,3 +323,30 @@ def test_config4_batch_bit_exact():
         g = maps[k].readback(spec.origin, tuple(spec.origin[a] + spec.dims[a] for a in range(3)))
         assert np.array_equal(g[0], ref[k][0]) and np.array_equal(g[1], ref[k][1]), k
         maps[k].close()
+
+
+def test_extreme_coordinates():
+    """Windows at the +-2^20 voxel limit, a sensor next to them and one
+    2^19 voxels away (rays of |D| ~ 2^29 in fixed point)."""
+    vs = 0.05
+    lim = 1 << 20
+    for case, (origin, dims) in enumerate([((lim - 24, -lim, lim - 16), (24, 32, 16)),
+                                           ((-lim, lim - 33, -lim + 5), (17, 33, 21))]):
+        om = oracle.OracleMap(dims, origin, vs, 3072, 64)
+        gm = gpu_map(dims, origin, vs, 3072, 64)
+        centre = np.array([(origin[a] + dims[a] / 2) * vs for a in range(3)])
+        for k, far in enumerate((0, 1 << 19)):
+            pose = synth.fuzz_pose((81, case, k), 0.0)
+            pose[:3, 3] = centre - np.array([far * vs * (1 if origin[0] > 0 else -1), 0.0, 0.0])
+            xyz = synth.fuzz_scan((82, case, k), 3000, extent_m=0.6, nan_frac=0.02)
+            if far:
+                # the same world points, seen from the far sensor
+                xyz = (xyz.astype(np.float64) + (centre - pose[:3, 3]) @ pose[:3, :3]).astype(np.float32)
+            say("extreme case", case, "sensor offset", far)
+            gst = gm.integrate(xyz, pose, stats=True)
+            ost = om.integrate(xyz, pose)
+            assert gst == ost, (case, k, gst, ost)
+            assert ost["voxels_updated"] > 0
+        assert_same_window(gm, om, dims)
+        gm.close()
+        om.close()
