@@ -207,6 +207,25 @@ tsdf_status tsdf_map_set_interpolation(tsdf_map *m, double vfov_deg, int32_t hli
 /* delta_z in 1/2^20 units, 0 when off. */
 tsdf_status tsdf_map_get_interpolation(const tsdf_map *m, int64_t *delta_q20);
 
+/* Surface extraction for inspection: the zero level set of the resident
+ * window inside the global voxel box [lo, hi) (which must lie inside the
+ * window), as triangles of 9 floats each (three vertices, x y z in metres,
+ * world frame) written to host memory tris. Marching tetrahedra: a cube is 8
+ * observed (w > 0) voxel centres g + {0,1}^3 in the box, cut into the 6
+ * tetrahedra around its diagonal from corner 0 to corner 7 (corner
+ * k = (k & 1, k >> 1 & 1, k >> 2 & 1)); vertices with sdf < 0 are inside;
+ * an edge from corner a to b crosses at t = s_a / (s_a - s_b) (float64),
+ * the point ((g_a + 1/2) + t (g_b - g_a)) voxel_size rounded to float32.
+ * Order: cubes by x, then y, then z; tetrahedra (0 1 3 7) (0 3 2 7)
+ * (0 2 6 7) (0 6 4 7) (0 4 5 7) (0 5 1 7); one inside or one outside
+ * vertex gives the triangle of its three edges in vertex order, two inside
+ * (i0 < i1) and two outside (o0 < o1) give (i0o0, i0o1, i1o1) and
+ * (i0o0, i1o1, i1o0). *n_tris gets the triangle count; tris = NULL (with
+ * max_tris = 0) only counts; TSDF_ERANGE if max_tris is below the count.
+ * Synchronous on the map's stream. */
+tsdf_status tsdf_mesh(tsdf_map *m, const int32_t lo[3], const int32_t hi[3], float *tris, int64_t max_tris,
+                      int64_t *n_tris);
+
 /* Candidate-buffer tiling of the integration: the window is cut into tiles
  * of 2^log2_tile[a] voxels per axis (each in [2, 6], z at least 3,
  * 2^9..2^12 voxels per tile; a tile's candidate keys live in 8 bytes of LDS

@@ -80,6 +80,8 @@ def lib():
         L.or_fill_offset.argtypes = [i64p, i64p, i64p, C.c_uint64, i64p, i64p, C.c_int64, i64p]
         L.or_set_interpolation.restype = C.c_int
         L.or_set_interpolation.argtypes = [C.c_void_p, C.c_int64]
+        L.or_mesh.restype = C.c_int64
+        L.or_mesh.argtypes = [C.c_void_p, i32p, i32p, C.POINTER(C.c_float), C.c_int64]
         L.or_recentre.restype = C.c_int
         L.or_recentre.argtypes = [i32p, i32p, C.c_double, C.POINTER(C.c_double), C.c_int64, C.c_int32,
                                   C.c_int, i32p]
@@ -270,6 +272,17 @@ class OracleMap:
         o = np.zeros(3, dtype=np.int32)
         lib().or_window(self._m, _p(sdf, C.c_int16), _p(w, C.c_int16), _p(o, C.c_int32))
         return sdf, w, tuple(int(v) for v in o)
+
+    def mesh(self, lo, hi) -> np.ndarray:
+        """Triangles (n, 3, 3) float32, metres, of the zero level set in the
+        resident box [lo, hi) (marching tetrahedra)."""
+        lo, hi = _i32(lo), _i32(hi)
+        n = int(lib().or_mesh(self._m, _p(lo, C.c_int32), _p(hi, C.c_int32), None, 0))
+        if n < 0:
+            raise ValueError("box outside the window")
+        out = np.zeros((max(n, 1), 9), np.float32)
+        lib().or_mesh(self._m, _p(lo, C.c_int32), _p(hi, C.c_int32), _p(out, C.c_float), n)
+        return out[:n].reshape(n, 3, 3)
 
     def store_chunks(self) -> int:
         return int(lib().or_store_chunks(self._m))

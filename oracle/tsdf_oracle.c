@@ -689,6 +689,99 @@ int or_readback(omap *m, const int32_t lo[3], const int32_t hi[3], int16_t *sdf,
     return OR_OK;
 }
 
+/* ------------------------------------------------------------------ */
+/* surface extraction for inspection: marching tetrahedra              */
+/* ------------------------------------------------------------------ */
+
+/* The zero level set of the resident window inside the box [lo, hi), as
+ * triangles (9 floats each: three vertices, x y z in metres, world frame).
+ * A cube is the 8 voxel centres g + {0,1}^3 with g and g + 1 in the box, all
+ * observed (w > 0). It is cut into the 6 tetrahedra around its diagonal from
+ * corner 0 to corner 7 (corner k = (k & 1, k >> 1 & 1, k >> 2 & 1)). In a
+ * tetrahedron, a vertex is inside when its sdf is negative; one inside (or
+ * one outside) vertex gives one triangle, two give two. An edge from
+ * corner a to b crosses at t = s_a / (s_a - s_b), the point
+ * (g_a + 1/2 + t (g_b - g_a)) voxel_size, in float64, then rounded to
+ * float32. Output order: cubes by x, then y, then z; tetrahedra in the
+ * order below; the triangles of a tetrahedron as listed below. Returns the
+ * number of triangles (writing at most max_tris), or -1 for a bad box. */
+static const int kTets[6][4] = {{0, 1, 3, 7}, {0, 3, 2, 7}, {0, 2, 6, 7}, {0, 6, 4, 7}, {0, 4, 5, 7}, {0, 5, 1, 7}};
+
+static void edge_point(const int64_t g[3], int a, int b, const int64_t s[8], double vs, float *out)
+{
+    const double t = (double)s[a] / ((double)s[a] - (double)s[b]);
+    for (int k = 0; k < 3; ++k) {
+        const double ga = (double)(g[k] + ((a >> k) & 1)) + 0.5;
+        const double gb = (double)(g[k] + ((b >> k) & 1)) + 0.5;
+        out[k] = (float)((ga + t * (gb - ga)) * vs);
+    }
+}
+
+int64_t or_mesh(omap *m, const int32_t lo[3], const int32_t hi[3], float *out, int64_t max_tris)
+{
+    if (!m || !lo || !hi) return -1;
+    for (int a = 0; a < 3; ++a)
+        if (hi[a] < lo[a] || lo[a] < m->origin[a] || hi[a] > (int64_t)m->origin[a] + m->dims[a]) return -1;
+    int64_t n = 0;
+    for (int64_t x = lo[0]; x + 1 < hi[0]; ++x)
+        for (int64_t y = lo[1]; y + 1 < hi[1]; ++y)
+            for (int64_t z = lo[2]; z + 1 < hi[2]; ++z) {
+                const int64_t g[3] = {x, y, z};
+                int64_t s[8];
+                int seen = 1;
+                for (int k = 0; k < 8 && seen; ++k) {
+                    const int64_t c[3] = {x + (k & 1), y + ((k >> 1) & 1), z + ((k >> 2) & 1)};
+                    const int64_t sl = slot_of(m, c);
+                    if (m->w[sl] <= 0) seen = 0;
+                    s[k] = m->sdf[sl];
+                }
+                if (!seen) continue;
+                for (int t = 0; t < 6; ++t) {
+                    const int *v = kTets[t];
+                    int in[4], nin = 0;
+                    for (int k = 0; k < 4; ++k) {
+                        in[k] = s[v[k]] < 0;
+                        nin += in[k];
+                    }
+                    if (nin == 0 || nin == 4) continue;
+                    float tri[2][9];
+                    int ntri;
+                    if (nin == 1 || nin == 3) {
+                        /* the lone vertex (inside when nin == 1, outside when 3) */
+                        int lone = 0;
+                        for (int k = 0; k < 4; ++k)
+                            if (in[k] == (nin == 1)) lone = k;
+                        int e = 0;
+                        for (int k = 0; k < 4; ++k)
+                            if (k != lone) edge_point(g, v[lone], v[k], s, m->voxel_size, &tri[0][3 * e++]);
+                        ntri = 1;
+                    } else {
+                        /* two inside (i0 < i1), two outside (o0 < o1): the quad
+                         * i0o0, i0o1, i1o1, i1o0 as two triangles */
+                        int i0 = -1, i1 = -1, o0 = -1, o1 = -1;
+                        for (int k = 0; k < 4; ++k) {
+                            if (in[k]) { if (i0 < 0) i0 = k; else i1 = k; }
+                            else { if (o0 < 0) o0 = k; else o1 = k; }
+                        }
+                        float q[4][3];
+                        edge_point(g, v[i0], v[o0], s, m->voxel_size, q[0]);
+                        edge_point(g, v[i0], v[o1], s, m->voxel_size, q[1]);
+                        edge_point(g, v[i1], v[o1], s, m->voxel_size, q[2]);
+                        edge_point(g, v[i1], v[o0], s, m->voxel_size, q[3]);
+                        const int order[6] = {0, 1, 2, 0, 2, 3};
+                        for (int k = 0; k < 6; ++k)
+                            for (int a = 0; a < 3; ++a) tri[k / 3][3 * (k % 3) + a] = q[order[k]][a];
+                        ntri = 2;
+                    }
+                    for (int k = 0; k < ntri; ++k) {
+                        if (out && n < max_tris) memcpy(&out[9 * n], tri[k], 9 * sizeof(float));
+                        ++n;
+                    }
+                }
+            }
+    return n;
+}
+
 /* The resident window in slot order (the raw device-layout view). */
 int or_window(omap *m, int16_t *sdf, int16_t *w, int32_t origin[3])
 {

@@ -21,7 +21,7 @@ EXPORTS = (
     "tsdf_map_device_arrays", "tsdf_recentre_origin", "tsdf_store_info", "tsdf_map_synchronize",
     "tsdf_profile_enable", "tsdf_profile_read", "tsdf_kernel_name", "tsdf_map_set_tiling",
     "tsdf_map_get_tiling", "tsdf_batch_release", "tsdf_set_graph_launch", "tsdf_batch_profile",
-    "tsdf_batch_profile_read", "tsdf_map_set_interpolation", "tsdf_map_get_interpolation",
+    "tsdf_batch_profile_read", "tsdf_map_set_interpolation", "tsdf_map_get_interpolation", "tsdf_mesh",
 )
 KERNELS = {"k_bin": 0, "k_tile": 1, "k_pack": 2, "k_unpack": 3}
 
@@ -76,6 +76,8 @@ def lib():
     L.tsdf_shift.argtypes = [vp, i32p]
     L.tsdf_readback.restype = st
     L.tsdf_readback.argtypes = [vp, i32p, i32p, C.POINTER(C.c_int16), C.POINTER(C.c_int16)]
+    L.tsdf_mesh.restype = st
+    L.tsdf_mesh.argtypes = [vp, i32p, i32p, C.POINTER(C.c_float), C.c_int64, C.POINTER(C.c_int64)]
     L.tsdf_map_set_interpolation.restype = st
     L.tsdf_map_set_interpolation.argtypes = [vp, C.c_double, C.c_int32]
     L.tsdf_map_get_interpolation.restype = st

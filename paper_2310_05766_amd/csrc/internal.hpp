@@ -125,6 +125,19 @@ struct InterpScan {
 };
 hipError_t launch_interp(const InterpScan &P, int64_t nvox, hipStream_t stream);
 
+// Surface extraction of a box of the window (mesh.hip).
+struct MeshArgs {
+    const int16_t *sdf, *w;
+    int32_t dims[3];  // the window (slot = floor_mod(g, dims))
+    int32_t lo[3];    // first cube's voxel
+    int64_t n[3];     // cubes per axis
+    int64_t ncubes;
+    double vs;        // voxel size, metres
+};
+int64_t mesh_blocks(int64_t ncubes);
+hipError_t launch_mesh_count(const MeshArgs &A, uint32_t *block_tris, hipStream_t stream);
+hipError_t launch_mesh_emit(const MeshArgs &A, const uint64_t *block_base, float *out, hipStream_t stream);
+
 // ---------------------------------------------------------------------------
 // Host-side store of 64^3-voxel chunks that left the window.
 // ---------------------------------------------------------------------------

@@ -623,6 +623,69 @@ tsdf_status tsdf_map_set_interpolation(tsdf_map *m, double vfov_deg, int32_t hli
     return TSDF_OK;
 }
 
+tsdf_status tsdf_mesh(tsdf_map *m, const int32_t lo[3], const int32_t hi[3], float *tris, int64_t max_tris,
+                      int64_t *n_tris)
+{
+    if (!m || !lo || !hi || !n_tris || max_tris < 0 || (max_tris > 0 && !tris)) return TSDF_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (hi[a] < lo[a] || lo[a] < m->d.origin[a] || (int64_t)hi[a] > (int64_t)m->d.origin[a] + m->d.dims[a])
+            return TSDF_EINVAL;
+    Guard g(m);
+    if (!g.ok) return TSDF_EBUSY;
+    if (m->poisoned) return TSDF_EDEVICE;
+    MeshArgs A;
+    A.sdf = m->sdf;
+    A.w = m->w;
+    A.ncubes = 1;
+    for (int a = 0; a < 3; ++a) {
+        A.dims[a] = m->d.dims[a];
+        A.lo[a] = lo[a];
+        A.n[a] = std::max<int64_t>(0, (int64_t)hi[a] - lo[a] - 1);
+        A.ncubes *= A.n[a];
+    }
+    A.vs = m->d.voxel_size_m;
+    *n_tris = 0;
+    if (A.ncubes == 0) return TSDF_OK;
+    const int64_t nb = mesh_blocks(A.ncubes);
+    uint32_t *bt = nullptr;
+    uint64_t *bb = nullptr;
+    float *out = nullptr;
+    std::vector<uint32_t> counts((size_t)nb);
+    std::vector<uint64_t> base((size_t)nb);
+    tsdf_status st = TSDF_OK;
+    auto done = [&](tsdf_status r) {
+        if (bt) (void)hipFree(bt);
+        if (bb) (void)hipFree(bb);
+        if (out) (void)hipFree(out);
+        return r;
+    };
+    if (hipMalloc(&bt, (size_t)nb * sizeof(uint32_t)) != hipSuccess) return done(TSDF_ENOMEM);
+    if (launch_mesh_count(A, bt, m->stream) != hipSuccess ||
+        hipMemcpyAsync(counts.data(), bt, (size_t)nb * sizeof(uint32_t), hipMemcpyDeviceToHost, m->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(m->stream) != hipSuccess)
+        return done(fail_device(m));
+    uint64_t total = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        base[(size_t)b] = total;
+        total += counts[(size_t)b];
+    }
+    *n_tris = (int64_t)total;
+    if (!tris || total == 0) return done(TSDF_OK);  // a query of the count
+    if ((uint64_t)max_tris < total) return done(TSDF_ERANGE);
+    if (hipMalloc(&bb, (size_t)nb * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc(&out, (size_t)total * 9 * sizeof(float)) != hipSuccess)
+        return done(TSDF_ENOMEM);
+    if (hipMemcpyAsync(bb, base.data(), (size_t)nb * sizeof(uint64_t), hipMemcpyHostToDevice, m->stream) !=
+            hipSuccess ||
+        launch_mesh_emit(A, bb, out, m->stream) != hipSuccess ||
+        hipMemcpyAsync(tris, out, (size_t)total * 9 * sizeof(float), hipMemcpyDeviceToHost, m->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(m->stream) != hipSuccess)
+        st = fail_device(m);
+    return done(st);
+}
+
 tsdf_status tsdf_map_get_interpolation(const tsdf_map *m, int64_t *delta_q20)
 {
     if (!m || !delta_q20) return TSDF_EINVAL;

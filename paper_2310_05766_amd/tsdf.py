@@ -169,6 +169,17 @@ class TsdfMap:
     def synchronize(self):
         check(_abi.lib().tsdf_map_synchronize(self._h), "tsdf_map_synchronize")
 
+    def mesh(self, lo, hi) -> np.ndarray:
+        """Triangles (n, 3, 3) float32, metres, of the zero level set in the
+        resident box [lo, hi) (marching tetrahedra, tsdf_mesh)."""
+        lo_a, hi_a = (C.c_int32 * 3)(*[int(v) for v in lo]), (C.c_int32 * 3)(*[int(v) for v in hi])
+        n = C.c_int64()
+        check(_abi.lib().tsdf_mesh(self._h, lo_a, hi_a, None, 0, C.byref(n)), "tsdf_mesh")
+        out = np.zeros((max(n.value, 1), 9), np.float32)
+        check(_abi.lib().tsdf_mesh(self._h, lo_a, hi_a, out.ctypes.data_as(C.POINTER(C.c_float)), n.value,
+                                   C.byref(n)), "tsdf_mesh")
+        return out[:n.value].reshape(-1, 3, 3)
+
     def set_interpolation(self, vfov_deg: float = 0.0, hlines: int = 0):
         """Vertical interpolation between scan lines for the following scans
         (vfov in degrees over hlines scan lines; vfov 0 turns it off).

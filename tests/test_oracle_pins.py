@@ -569,3 +569,67 @@ def test_interp_invariants_room_scan():
     assert int((ki != np.uint64(0xFFFFFFFFFFFFFFFF)).sum()) > int(held.sum())
     for m in (plain, off, on):
         m.close()
+
+
+# -- surface extraction for inspection (marching tetrahedra) -----------------
+
+def _tri_area(t):
+    a, b, c = (np.asarray(v, dtype=np.float64) for v in t)
+    return 0.5 * np.linalg.norm(np.cross(b - a, c - a))
+
+
+def test_mesh_of_a_plane_closed_form():
+    """Axis-parallel single-ray scans, one per (y, z) voxel centre of a 6 x 5
+    patch, all hitting the plane x = 20580/1024 voxels: the band voxels hold
+    the plane profile (golden/plane_profile.json), its sign changes between
+    voxels 19 and 20 at exactly t = 612/1024, so every vertex has
+    x = 20.09765625 voxels, and the triangles tile the patch between the ray
+    centres: 5 x 4 cubes, 8 triangles each, total area 20 voxel^2."""
+    vs = 0.25
+    m = oracle.OracleMap((32, 8, 8), (0, 0, 0), vs, 3072, 64)
+    for j in range(6):
+        for k in range(5):
+            pose = np.eye(4)
+            pose[:3, 3] = [0.5 * vs, (j + 0.5) * vs, (k + 0.5) * vs]
+            x = 20580 / 1024 * vs - 0.5 * vs
+            m.integrate(np.array([[x, 0.0, 0.0]], dtype=np.float32), pose)
+    tris = m.mesh((0, 0, 0), (32, 8, 8))
+    assert tris.shape == (5 * 4 * 8, 3, 3)
+    assert np.all(tris[:, :, 0] == np.float32(20.09765625 * vs))
+    area = sum(_tri_area(t) for t in tris)
+    assert abs(area - 20 * vs * vs) < 1e-5
+    ys, zs = tris[:, :, 1], tris[:, :, 2]
+    assert ys.min() == np.float32(0.5 * vs) and ys.max() == np.float32(5.5 * vs)
+    assert zs.min() == np.float32(0.5 * vs) and zs.max() == np.float32(4.5 * vs)
+    # a sub-box that leaves out the crossing layer has no surface
+    assert m.mesh((21, 0, 0), (32, 8, 8)).shape[0] == 0
+    with pytest.raises(ValueError):
+        m.mesh((0, 0, 0), (33, 8, 8))
+    m.close()
+
+
+def test_mesh_of_room_scan_is_consistent():
+    """Invariants on a real scan's map: every vertex lies on a segment
+    between two corners of a cube (the varying coordinates share one
+    fraction t or 1 - t) inside the box; the whole box's triangles are those
+    of its two halves, split on an x plane (the halves share that plane's
+    voxels, not a cube)."""
+    w = synth.config1()
+    spec, sc = w.maps[0], w.scans[0]
+    m = oracle.OracleMap.from_spec(spec)
+    m.integrate(sc.xyz, sc.pose)
+    lo, hi = spec.origin, tuple(spec.origin[a] + spec.dims[a] for a in range(3))
+    tris = m.mesh(lo, hi)
+    assert tris.shape[0] > 10000
+    vs = spec.voxel_size
+    v = tris.reshape(-1, 3).astype(np.float64) / vs - 0.5
+    f = v - np.floor(v)
+    for row in f[:: max(1, len(f) // 5000)]:
+        vary = [x for x in row if 1e-4 < x < 1 - 1e-4]
+        assert all(min(abs(x - vary[0]), abs(x - (1 - vary[0]))) < 1e-4 for x in vary), row
+    assert np.all((v >= np.array(lo) - 1e-4) & (v <= np.array(hi) - 1 + 1e-4))
+    mid = lo[0] + spec.dims[0] // 2
+    a = m.mesh(lo, (mid + 1, hi[1], hi[2]))
+    b = m.mesh((mid, lo[1], lo[2]), hi)
+    assert a.shape[0] + b.shape[0] == tris.shape[0]
+    m.close()
