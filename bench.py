@@ -452,6 +452,17 @@ def main():
             gm.synchronize()
             lat.append(time.perf_counter() - t1)
     lat_ms = np.array(lat) * 1e3
+    # surface extraction of the whole window after the sequence (inspection)
+    lo = spec.origin
+    hi = tuple(spec.origin[a] + spec.dims[a] for a in range(3))
+    gm.synchronize()
+    t0 = time.perf_counter()
+    tris = gm.mesh(lo, hi)
+    t_mesh = time.perf_counter() - t0
+    mesh = {"box": [list(lo), list(hi)], "triangles": int(tris.shape[0]), "ms": 1e3 * t_mesh,
+            "cubes_per_s": float(np.prod([spec.dims[a] - 1 for a in range(3)])) / t_mesh,
+            "includes": "count pass, host scan, emit pass, device-to-host copy of the triangles"}
+    del tris
     gm.close()
 
     shift = None if args.no_shift else shift_leg(torch, TsdfMap, synth)
@@ -524,6 +535,7 @@ def main():
             "achieved_GBps": B_batch / (kt["launch"]["avg_us"] * 1e-6) / 1e9,
         },
         "shift": shift,
+        "mesh": mesh,
         "uneven_batches": uneven,
         "interpolation": interp,
         "serving": serving,
