@@ -207,6 +207,32 @@ tsdf_status tsdf_map_set_interpolation(tsdf_map *m, double vfov_deg, int32_t hli
 /* delta_z in 1/2^20 units, 0 when off. */
 tsdf_status tsdf_map_get_interpolation(const tsdf_map *m, int64_t *delta_q20);
 
+/* Point-to-TSDF registration (the paper's stated next step, Sec. VIII;
+ * HATSDF localises directly in its TSDF, Sec. I). A scan point p lands at
+ * w = R p + t (float64, the integration's fma chain, metres); its residual
+ * is the map's signed distance phi(w) in metres, trilinear between the 8
+ * voxel centres around w, used only when all 8 are resident, observed and
+ * not truncated (|sdf| < tau). Damped Gauss-Newton on sum phi^2:
+ * (H + damping I) d = -J^T r with rows J = (grad phi, w x grad phi), then
+ * R' = exp([theta]x) R, t' = exp([theta]x) t + rho for d = (rho, theta);
+ * at most `iterations` steps (fewer when under 6 points remain or the
+ * system is singular). The map is only read. Normal-equation sums are
+ * formed in a fixed order (per block, then blocks in order), so results do
+ * not depend on scheduling. Synchronous on the map's stream. */
+typedef struct {
+    int64_t points_used; /* at the returned pose */
+    double cost;         /* sum of squared residuals there, m^2 */
+    double last_step;    /* norm of the last step d */
+    int32_t steps;       /* steps taken */
+} tsdf_register_info;
+tsdf_status tsdf_register_scan(tsdf_map *m, const float *xyz, int64_t n_points, tsdf_ptr_kind kind,
+                               const double init_pose[16], int32_t iterations, double damping,
+                               double pose_out[16], tsdf_register_info *info);
+/* The normal equations at one pose: sums[0..20] = H (upper triangle, row-
+ * major), sums[21..26] = J^T r, sums[27] = sum r^2, sums[28] = points used. */
+tsdf_status tsdf_register_sums(tsdf_map *m, const float *xyz, int64_t n_points, tsdf_ptr_kind kind,
+                               const double pose[16], double sums[29]);
+
 /* Surface extraction for inspection: the zero level set of the resident
  * window inside the global voxel box [lo, hi) (which must lie inside the
  * window), as triangles of 9 floats each (three vertices, x y z in metres,

@@ -80,6 +80,18 @@ def lib():
         L.or_fill_offset.argtypes = [i64p, i64p, i64p, C.c_uint64, i64p, i64p, C.c_int64, i64p]
         L.or_set_interpolation.restype = C.c_int
         L.or_set_interpolation.argtypes = [C.c_void_p, C.c_int64]
+        f64p = C.POINTER(C.c_double)
+        L.or_reg_point.restype = C.c_int
+        L.or_reg_point.argtypes = [C.c_void_p, C.POINTER(C.c_float), f64p, f64p, f64p, f64p]
+        L.or_reg_sums.restype = C.c_int
+        L.or_reg_sums.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int64, f64p, f64p]
+        L.or_reg_step.restype = C.c_int
+        L.or_reg_step.argtypes = [f64p, C.c_double, f64p, f64p, f64p]
+        L.or_register.restype = C.c_int
+        L.or_register.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int64, f64p, C.c_int32, C.c_double, f64p,
+                                  f64p]
+        L.or_set_voxels.restype = C.c_int
+        L.or_set_voxels.argtypes = [C.c_void_p, i32p, i32p, C.POINTER(C.c_int16), C.POINTER(C.c_int16)]
         L.or_mesh.restype = C.c_int64
         L.or_mesh.argtypes = [C.c_void_p, i32p, i32p, C.POINTER(C.c_float), C.c_int64]
         L.or_recentre.restype = C.c_int
@@ -179,6 +191,17 @@ def fill_offset(q, o, D, r, U, g, dq):
     return tuple(int(v) for v in e)
 
 
+def reg_step(sums, lam, pose):
+    """One damped Gauss-Newton step from normal-equation sums: (new pose, d)
+    or None when the system is not positive definite."""
+    S = np.ascontiguousarray(np.asarray(sums, dtype=np.float64))
+    M = np.ascontiguousarray(np.asarray(pose, dtype=np.float64).reshape(16))
+    out, d = np.zeros(16), np.zeros(6)
+    if not lib().or_reg_step(_p(S, C.c_double), float(lam), _p(M, C.c_double), _p(out, C.c_double), _p(d, C.c_double)):
+        return None
+    return out.reshape(4, 4), d
+
+
 def recentre(dims, origin, voxel_size, pose, radius_u, chunk=64, force=False):
     """(shift_due, new_origin) of the local-map recentre rule."""
     out = np.zeros(3, dtype=np.int32)
@@ -272,6 +295,40 @@ class OracleMap:
         o = np.zeros(3, dtype=np.int32)
         lib().or_window(self._m, _p(sdf, C.c_int16), _p(w, C.c_int16), _p(o, C.c_int32))
         return sdf, w, tuple(int(v) for v in o)
+
+    def set_voxels(self, lo, hi, sdf, w):
+        """Test helper: write a box of voxels (resident part only)."""
+        lo, hi = _i32(lo), _i32(hi)
+        s = np.ascontiguousarray(np.asarray(sdf, dtype=np.int16))
+        ww = np.ascontiguousarray(np.asarray(w, dtype=np.int16))
+        lib().or_set_voxels(self._m, _p(lo, C.c_int32), _p(hi, C.c_int32), _p(s, C.c_int16), _p(ww, C.c_int16))
+
+    def reg_point(self, p, pose):
+        """(phi metres, gradient per metre, world point) or None."""
+        pp = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        M = np.ascontiguousarray(np.asarray(pose, dtype=np.float64).reshape(16))
+        phi, g, w = np.zeros(1), np.zeros(3), np.zeros(3)
+        ok = lib().or_reg_point(self._m, _p(pp, C.c_float), _p(M, C.c_double), _p(phi, C.c_double),
+                                _p(g, C.c_double), _p(w, C.c_double))
+        return (float(phi[0]), g, w) if ok else None
+
+    def reg_sums(self, xyz, pose) -> np.ndarray:
+        x = np.ascontiguousarray(np.asarray(xyz, dtype=np.float32).reshape(-1, 3))
+        M = np.ascontiguousarray(np.asarray(pose, dtype=np.float64).reshape(16))
+        out = np.zeros(29)
+        lib().or_reg_sums(self._m, _p(x, C.c_float), x.shape[0], _p(M, C.c_double), _p(out, C.c_double))
+        return out
+
+    def register(self, xyz, pose0, iterations: int = 10, damping: float = 1e-6):
+        """Damped Gauss-Newton point-to-TSDF registration: (pose, info) with
+        info = points used, cost, last step norm, steps."""
+        x = np.ascontiguousarray(np.asarray(xyz, dtype=np.float32).reshape(-1, 3))
+        M = np.ascontiguousarray(np.asarray(pose0, dtype=np.float64).reshape(16))
+        out, info = np.zeros(16), np.zeros(4)
+        lib().or_register(self._m, _p(x, C.c_float), x.shape[0], _p(M, C.c_double), int(iterations), float(damping),
+                          _p(out, C.c_double), _p(info, C.c_double))
+        return out.reshape(4, 4), {"points": int(info[0]), "cost": float(info[1]), "step": float(info[2]),
+                                   "steps": int(info[3])}
 
     def mesh(self, lo, hi) -> np.ndarray:
         """Triangles (n, 3, 3) float32, metres, of the zero level set in the

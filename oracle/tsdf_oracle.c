@@ -782,6 +782,191 @@ int64_t or_mesh(omap *m, const int32_t lo[3], const int32_t hi[3], float *out, i
     return n;
 }
 
+/* ------------------------------------------------------------------ */
+/* point-to-TSDF registration (the paper's stated next step, Sec. VIII; */
+/* HATSDF registers scans directly in the TSDF, Sec. I)                  */
+/* ------------------------------------------------------------------ */
+
+/* Readings (the paper names the method, not its algorithm): a scan point p
+ * under the pose (R, t) lands at w = R p + t (the fixed fma chain of the
+ * integration, in metres). Its residual is the map's signed distance there,
+ * phi(w) in metres, trilinear between the 8 voxel centres around w; the
+ * point is used only when all 8 are resident, observed (weight > 0) and not
+ * truncated (|sdf| < tau). Gauss-Newton on sum phi^2 with a left update
+ * w' = R_d w + rho, R_d = exp([theta]x): the Jacobian row is
+ * J = (grad phi, w x grad phi). */
+int or_reg_point(omap *m, const float p[3], const double M[16], double *phi, double grad[3], double wout[3])
+{
+    if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) return 0;
+    const double x = (double)p[0], y = (double)p[1], z = (double)p[2];
+    double u[3], w[3];
+    int64_t i0[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+        w[a] = fma(M[4 * a + 0], x, fma(M[4 * a + 1], y, fma(M[4 * a + 2], z, M[4 * a + 3])));
+        u[a] = w[a] / m->voxel_size - 0.5;  /* voxel g's centre is at u = g */
+        if (!(fabs(u[a]) < 1073741824.0)) return 0;
+        const double fl = floor(u[a]);
+        i0[a] = (int64_t)fl;
+        f[a] = u[a] - fl;
+    }
+    double c[8];
+    for (int k = 0; k < 8; ++k) {
+        const int64_t g[3] = {i0[0] + (k & 1), i0[1] + ((k >> 1) & 1), i0[2] + ((k >> 2) & 1)};
+        if (!in_window(m->origin, m->dims, g)) return 0;
+        const int64_t sl = slot_of(m, g);
+        if (m->w[sl] <= 0) return 0;
+        const int64_t sq = m->sdf[sl];
+        if (sq <= -m->tau_u || sq >= m->tau_u) return 0;
+        c[k] = (double)sq * m->voxel_size / 1024.0; /* metres */
+    }
+    /* trilinear value and its derivatives along x, y, z (per voxel) */
+    const double c00 = c[0] + f[0] * (c[1] - c[0]), c10 = c[2] + f[0] * (c[3] - c[2]);
+    const double c01 = c[4] + f[0] * (c[5] - c[4]), c11 = c[6] + f[0] * (c[7] - c[6]);
+    const double c0 = c00 + f[1] * (c10 - c00), c1 = c01 + f[1] * (c11 - c01);
+    *phi = c0 + f[2] * (c1 - c0);
+    const double dx0 = (c[1] - c[0]) + f[1] * ((c[3] - c[2]) - (c[1] - c[0]));
+    const double dx1 = (c[5] - c[4]) + f[1] * ((c[7] - c[6]) - (c[5] - c[4]));
+    const double dx = dx0 + f[2] * (dx1 - dx0);
+    const double dy = (c10 - c00) + f[2] * ((c11 - c01) - (c10 - c00));
+    const double dz = c1 - c0;
+    grad[0] = dx / m->voxel_size;
+    grad[1] = dy / m->voxel_size;
+    grad[2] = dz / m->voxel_size;
+    for (int a = 0; a < 3; ++a) wout[a] = w[a];
+    return 1;
+}
+
+/* Normal equations at a pose: sums[0..20] = H (upper triangle, row-major),
+ * sums[21..26] = J^T r, sums[27] = sum r^2, sums[28] = points used. */
+int or_reg_sums(omap *m, const float *xyz, int64_t n, const double M[16], double sums[29])
+{
+    if (!m || n < 0 || (n > 0 && !xyz) || !M || !sums) return OR_EINVAL;
+    for (int k = 0; k < 29; ++k) sums[k] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double phi, gr[3], w[3];
+        if (!or_reg_point(m, &xyz[3 * i], M, &phi, gr, w)) continue;
+        const double J[6] = {gr[0], gr[1], gr[2], w[1] * gr[2] - w[2] * gr[1], w[2] * gr[0] - w[0] * gr[2],
+                             w[0] * gr[1] - w[1] * gr[0]};
+        int k = 0;
+        for (int a = 0; a < 6; ++a)
+            for (int b = a; b < 6; ++b) sums[k++] += J[a] * J[b];
+        for (int a = 0; a < 6; ++a) sums[21 + a] += J[a] * phi;
+        sums[27] += phi * phi;
+        sums[28] += 1.0;
+    }
+    return OR_OK;
+}
+
+/* One damped Gauss-Newton step from the sums: (H + lambda I) d = -J^T r by
+ * Cholesky, then R' = exp([theta]x) R, t' = exp([theta]x) t + rho for
+ * d = (rho, theta). Returns 0 when the system is not positive definite. */
+int or_reg_step(const double sums[29], double lambda, const double M[16], double Mout[16], double d[6])
+{
+    double A[6][6], b[6];
+    int k = 0;
+    for (int a = 0; a < 6; ++a)
+        for (int c = a; c < 6; ++c) A[a][c] = A[c][a] = sums[k++];
+    for (int a = 0; a < 6; ++a) {
+        A[a][a] += lambda;
+        b[a] = -sums[21 + a];
+    }
+    double L[6][6] = {{0}};
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double acc = A[i][j];
+            for (int q = 0; q < j; ++q) acc -= L[i][q] * L[j][q];
+            if (i == j) {
+                if (!(acc > 0.0)) return 0;
+                L[i][i] = sqrt(acc);
+            } else {
+                L[i][j] = acc / L[j][j];
+            }
+        }
+    double yv[6];
+    for (int i = 0; i < 6; ++i) {
+        double acc = b[i];
+        for (int q = 0; q < i; ++q) acc -= L[i][q] * yv[q];
+        yv[i] = acc / L[i][i];
+    }
+    for (int i = 5; i >= 0; --i) {
+        double acc = yv[i];
+        for (int q = i + 1; q < 6; ++q) acc -= L[q][i] * d[q];
+        d[i] = acc / L[i][i];
+    }
+    const double th[3] = {d[3], d[4], d[5]};
+    const double an = sqrt(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
+    const double K[3][3] = {{0, -th[2], th[1]}, {th[2], 0, -th[0]}, {-th[1], th[0], 0}};
+    double Rd[3][3];
+    const double s1 = an > 1e-12 ? sin(an) / an : 1.0;
+    const double s2 = an > 1e-12 ? (1.0 - cos(an)) / (an * an) : 0.5;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double kk = 0.0;
+            for (int q = 0; q < 3; ++q) kk += K[i][q] * K[q][j];
+            Rd[i][j] = (i == j ? 1.0 : 0.0) + s1 * K[i][j] + s2 * kk;
+        }
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int q = 0; q < 3; ++q) acc += Rd[i][q] * M[4 * q + j];
+            Mout[4 * i + j] = acc;
+        }
+        double acc = d[i];
+        for (int q = 0; q < 3; ++q) acc += Rd[i][q] * M[4 * q + 3];
+        Mout[4 * i + 3] = acc;
+    }
+    Mout[12] = 0.0; Mout[13] = 0.0; Mout[14] = 0.0; Mout[15] = 1.0;
+    return 1;
+}
+
+/* iterations damped Gauss-Newton steps from M0; info = {points used at the
+ * last pose, cost at the last pose, norm of the last step, steps taken}. */
+int or_register(omap *m, const float *xyz, int64_t n, const double M0[16], int32_t iterations, double lambda,
+                double Mout[16], double info[4])
+{
+    if (!m || !M0 || !Mout || iterations < 0 || !(lambda >= 0.0)) return OR_EINVAL;
+    double M[16], sums[29], d[6] = {0};
+    memcpy(M, M0, sizeof(M));
+    int32_t it = 0;
+    double step = 0.0;
+    for (; it < iterations; ++it) {
+        or_reg_sums(m, xyz, n, M, sums);
+        if (sums[28] < 6.0) break;
+        double Mn[16];
+        if (!or_reg_step(sums, lambda, M, Mn, d)) break;
+        memcpy(M, Mn, sizeof(M));
+        step = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + d[3] * d[3] + d[4] * d[4] + d[5] * d[5]);
+    }
+    or_reg_sums(m, xyz, n, M, sums);
+    memcpy(Mout, M, sizeof(M));
+    if (info) {
+        info[0] = sums[28];
+        info[1] = sums[27];
+        info[2] = step;
+        info[3] = it;
+    }
+    return OR_OK;
+}
+
+/* Test helper: write a box of voxels (resident part only). */
+int or_set_voxels(omap *m, const int32_t lo[3], const int32_t hi[3], const int16_t *sdf, const int16_t *w)
+{
+    if (!m || !lo || !hi || !sdf || !w) return OR_EINVAL;
+    int64_t ny = hi[1] - lo[1], nz = hi[2] - lo[2];
+    for (int64_t x = lo[0]; x < hi[0]; ++x)
+        for (int64_t y = lo[1]; y < hi[1]; ++y)
+            for (int64_t z = lo[2]; z < hi[2]; ++z) {
+                int64_t g[3] = {x, y, z};
+                if (!in_window(m->origin, m->dims, g)) continue;
+                int64_t o = ((x - lo[0]) * ny + (y - lo[1])) * nz + (z - lo[2]);
+                int64_t sl = slot_of(m, g);
+                m->sdf[sl] = sdf[o];
+                m->w[sl] = w[o];
+            }
+    return OR_OK;
+}
+
 /* The resident window in slot order (the raw device-layout view). */
 int or_window(omap *m, int16_t *sdf, int16_t *w, int32_t origin[3])
 {

@@ -22,6 +22,7 @@ EXPORTS = (
     "tsdf_profile_enable", "tsdf_profile_read", "tsdf_kernel_name", "tsdf_map_set_tiling",
     "tsdf_map_get_tiling", "tsdf_batch_release", "tsdf_set_graph_launch", "tsdf_batch_profile",
     "tsdf_batch_profile_read", "tsdf_map_set_interpolation", "tsdf_map_get_interpolation", "tsdf_mesh",
+    "tsdf_register_scan", "tsdf_register_sums",
 )
 KERNELS = {"k_bin": 0, "k_tile": 1, "k_pack": 2, "k_unpack": 3}
 
@@ -38,6 +39,10 @@ class ScanStats(C.Structure):
 
 class ScanDesc(C.Structure):
     _fields_ = [("map", C.c_void_p), ("xyz", C.c_void_p), ("n_points", C.c_int64), ("pose", C.c_double * 16)]
+
+
+class RegisterInfo(C.Structure):
+    _fields_ = [("points_used", C.c_int64), ("cost", C.c_double), ("last_step", C.c_double), ("steps", C.c_int32)]
 
 
 class TsdfError(RuntimeError):
@@ -76,6 +81,12 @@ def lib():
     L.tsdf_shift.argtypes = [vp, i32p]
     L.tsdf_readback.restype = st
     L.tsdf_readback.argtypes = [vp, i32p, i32p, C.POINTER(C.c_int16), C.POINTER(C.c_int16)]
+    f64p = C.POINTER(C.c_double)
+    L.tsdf_register_scan.restype = st
+    L.tsdf_register_scan.argtypes = [vp, C.POINTER(C.c_float), C.c_int64, C.c_int, f64p, C.c_int32, C.c_double, f64p,
+                                     C.POINTER(RegisterInfo)]
+    L.tsdf_register_sums.restype = st
+    L.tsdf_register_sums.argtypes = [vp, C.POINTER(C.c_float), C.c_int64, C.c_int, f64p, f64p]
     L.tsdf_mesh.restype = st
     L.tsdf_mesh.argtypes = [vp, i32p, i32p, C.POINTER(C.c_float), C.c_int64, C.POINTER(C.c_int64)]
     L.tsdf_map_set_interpolation.restype = st

@@ -125,6 +125,20 @@ struct InterpScan {
 };
 hipError_t launch_interp(const InterpScan &P, int64_t nvox, hipStream_t stream);
 
+// Point-to-TSDF registration sums (register.hip).
+constexpr int kRegSums = 29;  // H upper triangle (21), J^T r (6), sum r^2, points used
+struct RegArgs {
+    double M[12];      // pose rows 0..2
+    const float *xyz;  // device points
+    int64_t n;
+    const int16_t *sdf, *w;
+    int32_t dims[3], origin[3];
+    int32_t tau;
+    double vs;
+};
+int64_t reg_blocks(int64_t n);
+hipError_t launch_reg_sums(const RegArgs &A, double *partials, hipStream_t stream);
+
 // Surface extraction of a box of the window (mesh.hip).
 struct MeshArgs {
     const int16_t *sdf, *w;

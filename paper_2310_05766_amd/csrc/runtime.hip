@@ -623,6 +623,175 @@ tsdf_status tsdf_map_set_interpolation(tsdf_map *m, double vfov_deg, int32_t hli
     return TSDF_OK;
 }
 
+// Normal equations of the registration at pose M, on device points xyz
+// (the map's stream; synchronous): sums in block order.
+static tsdf_status reg_sums_dev(tsdf_map *m, const float *xyz, int64_t n, const double M[16], double *partials,
+                                std::vector<double> &host, double sums[kRegSums])
+{
+    RegArgs A;
+    for (int k = 0; k < 12; ++k) A.M[k] = M[k];
+    A.xyz = xyz;
+    A.n = n;
+    A.sdf = m->sdf;
+    A.w = m->w;
+    for (int a = 0; a < 3; ++a) {
+        A.dims[a] = m->d.dims[a];
+        A.origin[a] = m->d.origin[a];
+    }
+    A.tau = m->d.tau_q10;
+    A.vs = m->d.voxel_size_m;
+    for (int k = 0; k < kRegSums; ++k) sums[k] = 0.0;
+    const int64_t nb = reg_blocks(n);
+    if (nb == 0) return TSDF_OK;
+    HIPCHK(m, launch_reg_sums(A, partials, m->stream));
+    HIPCHK(m, hipMemcpyAsync(host.data(), partials, (size_t)nb * kRegSums * sizeof(double), hipMemcpyDeviceToHost,
+                             m->stream));
+    HIPCHK(m, hipStreamSynchronize(m->stream));
+    for (int64_t b = 0; b < nb; ++b)
+        for (int k = 0; k < kRegSums; ++k) sums[k] += host[(size_t)(b * kRegSums + k)];
+    return TSDF_OK;
+}
+
+// (H + lambda I) d = -g by Cholesky; then the pose exp([theta]x) applied on
+// the left with translation rho (d = (rho, theta)). false when H + lambda I
+// is not positive definite.
+static bool reg_update(const double sums[kRegSums], double lambda, const double M[16], double out[16], double d[6])
+{
+    double H[6][6], L[6][6] = {{0}}, y[6];
+    for (int a = 0, k = 0; a < 6; ++a)
+        for (int b = a; b < 6; ++b, ++k) H[a][b] = H[b][a] = sums[k];
+    for (int a = 0; a < 6; ++a) H[a][a] += lambda;
+    for (int i = 0; i < 6; ++i) {
+        for (int j = 0; j < i; ++j) {
+            double s = H[i][j];
+            for (int q = 0; q < j; ++q) s -= L[i][q] * L[j][q];
+            L[i][j] = s / L[j][j];
+        }
+        double s = H[i][i];
+        for (int q = 0; q < i; ++q) s -= L[i][q] * L[i][q];
+        if (!(s > 0.0)) return false;
+        L[i][i] = sqrt(s);
+    }
+    for (int i = 0; i < 6; ++i) {
+        double s = -sums[21 + i];
+        for (int q = 0; q < i; ++q) s -= L[i][q] * y[q];
+        y[i] = s / L[i][i];
+    }
+    for (int i = 5; i >= 0; --i) {
+        double s = y[i];
+        for (int q = i + 1; q < 6; ++q) s -= L[q][i] * d[q];
+        d[i] = s / L[i][i];
+    }
+    const double ax = d[3], ay = d[4], az = d[5];
+    const double ang = sqrt(ax * ax + ay * ay + az * az);
+    const double a = ang > 1e-12 ? sin(ang) / ang : 1.0;
+    const double b = ang > 1e-12 ? (1.0 - cos(ang)) / (ang * ang) : 0.5;
+    // exp(K) = I + a K + b K^2, K = [theta]x
+    const double K[3][3] = {{0.0, -az, ay}, {az, 0.0, -ax}, {-ay, ax, 0.0}};
+    double R[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double k2 = 0.0;
+            for (int q = 0; q < 3; ++q) k2 += K[i][q] * K[q][j];
+            R[i][j] = (i == j ? 1.0 : 0.0) + a * K[i][j] + b * k2;
+        }
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 4; ++j) {
+            double s = j == 3 ? d[i] : 0.0;
+            for (int q = 0; q < 3; ++q) s += R[i][q] * M[4 * q + j];
+            out[4 * i + j] = s;
+        }
+    }
+    out[12] = out[13] = out[14] = 0.0;
+    out[15] = 1.0;
+    return true;
+}
+
+// Device copy of a scan's points for the registration calls.
+static tsdf_status reg_points(tsdf_map *m, const float *xyz, int64_t n, bool host, const float **dev)
+{
+    *dev = xyz;
+    if (!host || n == 0) return TSDF_OK;
+    if (n > m->interp_pts_cap) {
+        HIPCHK(m, hipStreamSynchronize(m->stream));
+        if (m->interp_pts) HIPCHK(m, hipFree(m->interp_pts));
+        m->interp_pts = nullptr;
+        m->interp_pts_cap = 0;
+        if (hipMalloc(&m->interp_pts, (size_t)n * 3 * sizeof(float)) != hipSuccess) return TSDF_ENOMEM;
+        m->interp_pts_cap = n;
+    }
+    HIPCHK(m, hipMemcpyAsync(m->interp_pts, xyz, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, m->stream));
+    HIPCHK(m, hipStreamSynchronize(m->stream));
+    *dev = m->interp_pts;
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_register_sums(tsdf_map *m, const float *xyz, int64_t n_points, tsdf_ptr_kind kind,
+                               const double pose[16], double sums[29])
+{
+    if (!m || !pose || !sums || n_points < 0 || (n_points > 0 && !xyz)) return TSDF_EINVAL;
+    if (kind != TSDF_PTR_HOST && kind != TSDF_PTR_DEVICE) return TSDF_EINVAL;
+    for (int k = 0; k < 12; ++k)
+        if (!std::isfinite(pose[k])) return TSDF_EINVAL;
+    Guard g(m);
+    if (!g.ok) return TSDF_EBUSY;
+    if (m->poisoned) return TSDF_EDEVICE;
+    const float *dev;
+    tsdf_status st = reg_points(m, xyz, n_points, kind == TSDF_PTR_HOST, &dev);
+    if (st != TSDF_OK) return st;
+    const int64_t nb = reg_blocks(n_points);
+    double *partials = nullptr;
+    if (nb > 0 && hipMalloc(&partials, (size_t)nb * kRegSums * sizeof(double)) != hipSuccess) return TSDF_ENOMEM;
+    std::vector<double> host((size_t)nb * kRegSums);
+    st = reg_sums_dev(m, dev, n_points, pose, partials, host, sums);
+    if (partials) (void)hipFree(partials);
+    return st;
+}
+
+tsdf_status tsdf_register_scan(tsdf_map *m, const float *xyz, int64_t n_points, tsdf_ptr_kind kind,
+                               const double init_pose[16], int32_t iterations, double damping, double pose_out[16],
+                               tsdf_register_info *info)
+{
+    if (!m || !init_pose || !pose_out || n_points < 0 || (n_points > 0 && !xyz) || iterations < 0 ||
+        !(damping >= 0.0) || !std::isfinite(damping))
+        return TSDF_EINVAL;
+    if (kind != TSDF_PTR_HOST && kind != TSDF_PTR_DEVICE) return TSDF_EINVAL;
+    for (int k = 0; k < 12; ++k)
+        if (!std::isfinite(init_pose[k])) return TSDF_EINVAL;
+    Guard g(m);
+    if (!g.ok) return TSDF_EBUSY;
+    if (m->poisoned) return TSDF_EDEVICE;
+    const float *dev;
+    tsdf_status st = reg_points(m, xyz, n_points, kind == TSDF_PTR_HOST, &dev);
+    if (st != TSDF_OK) return st;
+    const int64_t nb = reg_blocks(n_points);
+    double *partials = nullptr;
+    if (nb > 0 && hipMalloc(&partials, (size_t)nb * kRegSums * sizeof(double)) != hipSuccess) return TSDF_ENOMEM;
+    std::vector<double> host((size_t)nb * kRegSums);
+    double M[16], sums[kRegSums], d[6] = {0, 0, 0, 0, 0, 0}, step = 0.0;
+    memcpy(M, init_pose, sizeof(M));
+    int32_t it = 0;
+    for (; it < iterations && st == TSDF_OK; ++it) {
+        st = reg_sums_dev(m, dev, n_points, M, partials, host, sums);
+        if (st != TSDF_OK || sums[28] < 6.0) break;
+        double Mn[16];
+        if (!reg_update(sums, damping, M, Mn, d)) break;
+        memcpy(M, Mn, sizeof(M));
+        step = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + d[3] * d[3] + d[4] * d[4] + d[5] * d[5]);
+    }
+    if (st == TSDF_OK) st = reg_sums_dev(m, dev, n_points, M, partials, host, sums);
+    if (partials) (void)hipFree(partials);
+    if (st != TSDF_OK) return st;
+    memcpy(pose_out, M, sizeof(M));
+    if (info) {
+        info->points_used = (int64_t)sums[28];
+        info->cost = sums[27];
+        info->last_step = step;
+        info->steps = it;
+    }
+    return TSDF_OK;
+}
+
 tsdf_status tsdf_mesh(tsdf_map *m, const int32_t lo[3], const int32_t hi[3], float *tris, int64_t max_tris,
                       int64_t *n_tris)
 {

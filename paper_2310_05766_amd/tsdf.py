@@ -169,6 +169,28 @@ class TsdfMap:
     def synchronize(self):
         check(_abi.lib().tsdf_map_synchronize(self._h), "tsdf_map_synchronize")
 
+    def register(self, xyz, init_pose, iterations: int = 10, damping: float = 1e-6):
+        """Point-to-TSDF registration of a scan against this map: (pose,
+        info) with info = points_used, cost, last_step, steps."""
+        ptr, n, kind, keep = _points_arg(xyz)
+        M, Mp = _pose_arg(init_pose)
+        out = np.zeros(16)
+        info = _abi.RegisterInfo()
+        check(_abi.lib().tsdf_register_scan(self._h, C.cast(ptr, C.POINTER(C.c_float)), n, kind, Mp,
+                                            int(iterations), float(damping),
+                                            out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(info)),
+              "tsdf_register_scan")
+        return out.reshape(4, 4), {"points": int(info.points_used), "cost": float(info.cost),
+                                   "step": float(info.last_step), "steps": int(info.steps)}
+
+    def register_sums(self, xyz, pose) -> np.ndarray:
+        ptr, n, kind, keep = _points_arg(xyz)
+        M, Mp = _pose_arg(pose)
+        out = np.zeros(29)
+        check(_abi.lib().tsdf_register_sums(self._h, C.cast(ptr, C.POINTER(C.c_float)), n, kind, Mp,
+                                            out.ctypes.data_as(C.POINTER(C.c_double))), "tsdf_register_sums")
+        return out
+
     def mesh(self, lo, hi) -> np.ndarray:
         """Triangles (n, 3, 3) float32, metres, of the zero level set in the
         resident box [lo, hi) (marching tetrahedra, tsdf_mesh)."""
