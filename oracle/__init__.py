@@ -80,6 +80,8 @@ def lib():
         L.or_fill_offset.argtypes = [i64p, i64p, i64p, C.c_uint64, i64p, i64p, C.c_int64, i64p]
         L.or_set_interpolation.restype = C.c_int
         L.or_set_interpolation.argtypes = [C.c_void_p, C.c_int64]
+        L.or_set_carving.restype = C.c_int
+        L.or_set_carving.argtypes = [C.c_void_p, C.c_int]
         f64p = C.POINTER(C.c_double)
         L.or_reg_point.restype = C.c_int
         L.or_reg_point.argtypes = [C.c_void_p, C.POINTER(C.c_float), f64p, f64p, f64p, f64p]
@@ -251,6 +253,12 @@ class OracleMap:
         if lib().or_set_interpolation(self._m, d) != 0:
             raise ValueError("interpolation angle out of range")
         return d
+
+    def set_carving(self, on: bool = True):
+        """Free-space carving for the following scans: each ray is walked from
+        the sensor to the end of its band (not with interpolation)."""
+        if lib().or_set_carving(self._m, 1 if on else 0) != 0:
+            raise ValueError("carving is not available together with interpolation")
 
     def integrate(self, xyz, pose) -> dict:
         x = np.ascontiguousarray(np.asarray(xyz, dtype=np.float32).reshape(-1, 3))

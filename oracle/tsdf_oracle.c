@@ -239,15 +239,20 @@ int or_segment_voxels(const int64_t S[3], const int64_t E[3], int64_t *out, int 
 
 /* s = clamp(rdiv((q - c) . D, r), -tau, +tau) with c the voxel centre in
  * fixed point (c = 1024 g + 512): the voxel centre projected onto the ray
- * and measured from the scan point, positive on the sensor side. */
+ * and measured from the scan point, positive on the sensor side. The dot
+ * product is formed in 128 bits: for a voxel near the sensor of a long ray
+ * (free-space carving) it reaches about 3 * 2^62. */
 int64_t or_voxel_sdf(const int64_t q[3], const int64_t D[3], uint64_t r, const int64_t g[3], int64_t tau_u)
 {
-    int64_t dot = 0;
-    for (int a = 0; a < 3; ++a) dot += (q[a] - (1024 * g[a] + 512)) * D[a];
-    int64_t s = or_rdiv(dot, (int64_t)r);
+    __int128 dot = 0;
+    for (int a = 0; a < 3; ++a) dot += (__int128)(q[a] - (1024 * g[a] + 512)) * D[a];
+    /* rdiv in 128 bits: sign(dot) floor((2 |dot| + r) / 2r) */
+    const __int128 mag = dot < 0 ? -dot : dot;
+    const __int128 k = (2 * mag + (__int128)r) / (2 * (__int128)r);
+    __int128 s = dot < 0 ? -k : k;
     if (s > tau_u) s = tau_u;
     if (s < -tau_u) s = -tau_u;
-    return s;
+    return (int64_t)s;
 }
 
 /* key = |s| << 48 | i << 16 | (uint16)s. The smallest key of a voxel is the
@@ -334,6 +339,7 @@ typedef struct omap_s {
     double voxel_size, scale;
     int64_t tau_u, w_max;
     int64_t interp_dq; /* vertical interpolation: delta_z in 1/2^20 units, 0 = off */
+    int carve;         /* free-space carving: every ray is walked from the sensor */
     int64_t nvox;
     int16_t *sdf, *w; /* resident window, slot = floor_mod(g, dims) */
     uint64_t *K;      /* per-scan volume V as candidate keys, EMPTY = none */
@@ -499,7 +505,8 @@ static int build_volume(omap *m, const float *xyz, int64_t n, const double M[16]
     int64_t cap = 4096;
     int64_t *vox = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)cap);
     if (!vox) return OR_ENOMEM;
-    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)cap);
+    const int64_t fcap = 4096; /* a fill segment spans at most 2 * 64 voxels per axis */
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)fcap);
     if (!fill) { free(vox); return OR_ENOMEM; }
     int64_t U[3];
     or_up_vector(M, U);
@@ -511,35 +518,55 @@ static int build_volume(omap *m, const float *xyz, int64_t n, const double M[16]
         if (!or_quantise_point(&xyz[3 * i], M, m->scale, q)) continue;
         if (!or_band(q, o, m->tau_u, D, &r, S, E)) continue;
         (*valid)++;
-        int nv = or_segment_voxels(S, E, vox, (int)cap);
-        if (nv < 0) { free(vox); free(fill); return OR_ENOMEM; }
-        for (int k = 0; k < nv; ++k) {
-            int64_t *g = &vox[3 * k];
-            int64_t s = or_voxel_sdf(q, D, r, g, m->tau_u);
-            uint64_t key = or_key(s, (uint64_t)i);
-            /* the voxels this band voxel gives its value to: itself, or with
-             * vertical interpolation the floor-set of [c - e, c + e] (a band
-             * voxel outside the window may still fill voxels inside it) */
-            int nf = 1;
-            const int64_t *fv = g;
-            if (m->interp_dq > 0) {
-                int64_t e[3], A[3], Bv[3];
-                or_fill_offset(q, o, D, r, U, g, m->interp_dq, e);
-                for (int a = 0; a < 3; ++a) {
-                    A[a] = 1024 * g[a] + 512 - e[a];
-                    Bv[a] = 1024 * g[a] + 512 + e[a];
-                }
-                nf = or_segment_voxels(A, Bv, fill, (int)cap);
-                if (nf < 0) { free(vox); free(fill); return OR_ENOMEM; }
-                fv = fill;
+        /* the band [S, E]; with free-space carving (rays longer than tau)
+         * first the free-space segment [o, S] from the sensor to the start
+         * of the band, whose voxels receive this ray's distance the same way
+         * (the ray traversed from p towards the point). Visits count both
+         * segments, so the voxel where they meet counts twice. */
+        const int nseg = (m->carve && (int64_t)r > m->tau_u) ? 2 : 1;
+        for (int sg = 0; sg < nseg; ++sg) {
+            const int64_t *A0 = (nseg == 2 && sg == 0) ? o : S;
+            const int64_t *A1 = (nseg == 2 && sg == 0) ? S : E;
+            /* a segment touches at most 1 + sum_a (|L_a| / 1024 + 1) voxels */
+            int64_t need = 4;
+            for (int a = 0; a < 3; ++a) need += (A1[a] > A0[a] ? A1[a] - A0[a] : A0[a] - A1[a]) / 1024 + 1;
+            if (need > cap) {
+                if (need > ((int64_t)1 << 30)) { free(vox); free(fill); return OR_ENOMEM; }
+                int64_t *nvx = (int64_t *)realloc(vox, sizeof(int64_t) * 3 * (size_t)need);
+                if (!nvx) { free(vox); free(fill); return OR_ENOMEM; }
+                vox = nvx;
+                cap = need;
             }
-            for (int f = 0; f < nf; ++f) {
-                const int64_t *gf = &fv[3 * f];
-                if (!in_window(m->origin, m->dims, gf)) continue;
-                (*visits)++;
-                int64_t sl = slot_of(m, gf);
-                if (m->K[sl] == KEY_EMPTY) m->touched[m->ntouched++] = sl;
-                if (key < m->K[sl]) m->K[sl] = key;
+            int nv = or_segment_voxels(A0, A1, vox, (int)cap);
+            if (nv < 0) { free(vox); free(fill); return OR_ENOMEM; }
+            for (int k = 0; k < nv; ++k) {
+                int64_t *g = &vox[3 * k];
+                int64_t s = or_voxel_sdf(q, D, r, g, m->tau_u);
+                uint64_t key = or_key(s, (uint64_t)i);
+                /* the voxels this band voxel gives its value to: itself, or with
+                 * vertical interpolation the floor-set of [c - e, c + e] (a band
+                 * voxel outside the window may still fill voxels inside it) */
+                int nf = 1;
+                const int64_t *fv = g;
+                if (m->interp_dq > 0) {
+                    int64_t e[3], A[3], Bv[3];
+                    or_fill_offset(q, o, D, r, U, g, m->interp_dq, e);
+                    for (int a = 0; a < 3; ++a) {
+                        A[a] = 1024 * g[a] + 512 - e[a];
+                        Bv[a] = 1024 * g[a] + 512 + e[a];
+                    }
+                    nf = or_segment_voxels(A, Bv, fill, (int)fcap);
+                    if (nf < 0) { free(vox); free(fill); return OR_ENOMEM; }
+                    fv = fill;
+                }
+                for (int f = 0; f < nf; ++f) {
+                    const int64_t *gf = &fv[3 * f];
+                    if (!in_window(m->origin, m->dims, gf)) continue;
+                    (*visits)++;
+                    int64_t sl = slot_of(m, gf);
+                    if (m->K[sl] == KEY_EMPTY) m->touched[m->ntouched++] = sl;
+                    if (key < m->K[sl]) m->K[sl] = key;
+                }
             }
         }
     }
@@ -577,7 +604,21 @@ static int64_t merge_volume(omap *m)
 int or_set_interpolation(omap *m, int64_t dq)
 {
     if (!m || dq < 0 || dq >= ((int64_t)1 << 20)) return OR_EINVAL;
+    if (dq > 0 && m->carve) return OR_EINVAL; /* not together with carving */
     m->interp_dq = dq;
+    return OR_OK;
+}
+
+/* Free-space carving for the following scans (on = 1): each ray longer than
+ * tau also walks the segment [o, S] from the sensor position to the start
+ * of its band, so the voxels in front of the surface receive their (mostly
+ * truncated, +tau) distance as well; the band is unchanged. Not together
+ * with vertical interpolation. */
+int or_set_carving(omap *m, int on)
+{
+    if (!m || (on != 0 && on != 1)) return OR_EINVAL;
+    if (on && m->interp_dq > 0) return OR_EINVAL;
+    m->carve = on;
     return OR_OK;
 }
 

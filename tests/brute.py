@@ -89,13 +89,14 @@ def isqrt_floor(n: int) -> int:
     return lo
 
 
-def volume_brute(xyz, M, scale, tau_u, origin, dims):
+def volume_brute(xyz, M, scale, tau_u, origin, dims, carve=False):
     """Per-scan candidate volume over a small window by brute force.
 
     For every voxel of the window and every ray, the ray contributes if its
     band segment touches the voxel (exact interval test); the voxel keeps the
-    candidate with the smallest |s|, ties to the lowest point index. Returns
-    a dict g -> (|s|, i, s)."""
+    candidate with the smallest |s|, ties to the lowest point index. With
+    carve, a ray longer than tau also reaches the voxels of the segment from
+    the sensor to the start of its band. Returns a dict g -> (|s|, i, s)."""
     o = [round(M[a][3] * scale) for a in range(3)]
     lo = tuple(origin)
     hi = tuple(origin[a] + dims[a] for a in range(3))
@@ -112,7 +113,10 @@ def volume_brute(xyz, M, scale, tau_u, origin, dims):
         off = [round_half_away(Fraction(tau_u * D[a], r)) for a in range(3)]
         E = [q[a] + off[a] for a in range(3)]
         S = list(o) if r <= tau_u else [q[a] - off[a] for a in range(3)]
-        for g in segment_voxels_brute(S, E, lo, hi):
+        touched = set(segment_voxels_brute(S, E, lo, hi))
+        if carve and r > tau_u:
+            touched |= set(segment_voxels_brute(o, S, lo, hi))
+        for g in touched:
             c = [1024 * g[a] + 512 for a in range(3)]
             dot = sum((q[a] - c[a]) * D[a] for a in range(3))
             s = max(-tau_u, min(tau_u, round_half_away(Fraction(dot, r))))

@@ -744,3 +744,165 @@ def test_reg_recovers_a_perturbed_pose():
     assert ang < 0.5
     assert info["cost"] / info["points"] < cost0[27] / cost0[28]
     m.close()
+
+
+# -- free-space carving: the ray walked from the sensor ----------------------
+
+def _carve_axis_case(sensor_x, X):
+    """One ray along x from a voxel centre at sensor_x to the point at X
+    (metres = voxels): with carving, every voxel from the sensor's to the
+    band end's receives clamp(q_x - c_x, +-tau), and no other voxel; the
+    voxel where the free-space segment meets the band is visited twice."""
+    tau = 3072
+    m = oracle.OracleMap((80, 8, 8), (0, 0, 0), 1.0, tau, 64)
+    m.set_carving(True)
+    pose = np.eye(4)
+    pose[:3, 3] = [sensor_x, 4.5, 3.5]
+    xyz = np.array([[X - sensor_x, 0.0, 0.0]], dtype=np.float32)
+    st = m.integrate(xyz, pose)
+    sdf, w = m.readback((0, 0, 0), (80, 8, 8))
+    m.close()
+    ox = int(round(sensor_x * 1024))
+    qx = int(round(float(np.float32(X - sensor_x)) * 1024)) + ox
+    sgn = 1 if qx > ox else -1
+    ex = qx + sgn * tau  # off = rdiv(tau D, r) = tau sign(D) on an axis ray
+    want_sdf = np.zeros((80, 8, 8), dtype=np.int16)
+    want_w = np.zeros((80, 8, 8), dtype=np.int16)
+    for gx in range(min(ox, ex) // 1024, max(ox, ex) // 1024 + 1):
+        if 0 <= gx < 80:
+            s = sgn * (qx - (1024 * gx + 512))  # (q - c) . D / r along the ray
+            want_sdf[gx, 4, 3] = max(-tau, min(tau, s))
+            want_w[gx, 4, 3] = 1
+    return st, sdf, w, want_sdf, want_w
+
+
+@pytest.mark.parametrize("sensor_x,X", [(0.5, 30.2), (70.5, 20.3), (2.5, 77.9), (5.5, 0.25)])
+def test_carve_axis_ray_closed_form(sensor_x, X):
+    st, sdf, w, want_sdf, want_w = _carve_axis_case(sensor_x, X)
+    assert np.array_equal(sdf, want_sdf)
+    assert np.array_equal(w, want_w)
+    assert st["voxels_updated"] == int(want_w.sum())
+    assert st["visits"] == st["voxels_updated"] + 1
+
+
+@pytest.mark.parametrize("seed", [71, 72, 73, 74])
+def test_carve_volume_vs_brute_force(seed):
+    """The carved volume over an 8^3 window against the brute-force interval
+    test on the band and on the segment from the sensor to the band's start
+    (sensors inside and outside the window, NaNs and index ties), and the
+    visit count against the number of (segment, window voxel) incidences."""
+    vs, tau = 0.5, 1536
+    scale = 1024.0 / vs
+    dims, origin = (8, 8, 8), (-4, -4, -4)
+    xyz = _tiny_scan(seed, 20)
+    M = synth.fuzz_pose(seed, max_t=0.8 if seed % 2 else 3.0)
+    m = oracle.OracleMap(dims, origin, vs, tau, 64)
+    m.set_carving(True)
+    keys = m.volume(xyz, M)
+    best = brute.volume_brute(xyz, M, scale, tau, origin, dims, carve=True)
+    seen = 0
+    for gx in range(origin[0], origin[0] + 8):
+        for gy in range(origin[1], origin[1] + 8):
+            for gz in range(origin[2], origin[2] + 8):
+                kk = int(keys[gx % 8, gy % 8, gz % 8])
+                if (gx, gy, gz) in best:
+                    a, i, s = best[(gx, gy, gz)]
+                    assert kk == (a << 48) | (i << 16) | (s & 0xFFFF)
+                    seen += 1
+                else:
+                    assert kk == 0xFFFFFFFFFFFFFFFF
+    assert seen > 10
+    # visits: every (ray, window voxel) pair the segment from the sensor touches
+    o = [round(M[a][3] * scale) for a in range(3)]
+    lo, hi = tuple(origin), tuple(origin[a] + dims[a] for a in range(3))
+    visits = 0
+    for p in xyz:
+        q = brute.quantise(p, M, scale)
+        if q is None or q == o:
+            continue
+        D = [q[a] - o[a] for a in range(3)]
+        r = brute.isqrt_floor(sum(d * d for d in D))
+        off = [brute.round_half_away(Fraction(tau * D[a], r)) for a in range(3)]
+        E = [q[a] + off[a] for a in range(3)]
+        S = o if r <= tau else [q[a] - off[a] for a in range(3)]
+        visits += len(brute.segment_voxels_brute(S, E, lo, hi))
+        if r > tau:
+            visits += len(brute.segment_voxels_brute(o, S, lo, hi))
+    st = m.integrate(xyz, M)
+    assert st["visits"] == visits
+    m.close()
+
+
+def test_carve_equals_band_for_short_rays():
+    """Rays no longer than tau already start at the sensor: carving changes
+    nothing."""
+    tau = 3072  # 3 voxels at 0.1 m: points within 0.3 m
+    g = np.random.default_rng(75)
+    d = g.normal(size=(300, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    xyz = (d * g.uniform(0.02, 0.29, size=(300, 1))).astype(np.float32)
+    pose = synth.fuzz_pose(76, 0.5)
+    a = oracle.OracleMap((16, 16, 16), (-8, -8, -8), 0.1, tau, 64)
+    b = oracle.OracleMap((16, 16, 16), (-8, -8, -8), 0.1, tau, 64)
+    b.set_carving(True)
+    assert np.array_equal(a.volume(xyz, pose), b.volume(xyz, pose))
+    a.close()
+    b.close()
+
+
+def test_carve_superset_of_band_room_scan():
+    """Carving adds candidates and removes none: every voxel's key is at most
+    its band-only key, every band voxel is still visited, and the carved-only
+    voxels hold what the free space in front of the surfaces gives."""
+    w = synth.config1()
+    spec, sc = w.maps[0], w.scans[0]
+    xyz = sc.xyz[::7]
+    a = oracle.OracleMap.from_spec(spec)
+    b = oracle.OracleMap.from_spec(spec)
+    b.set_carving(True)
+    ka = a.volume(xyz, sc.pose)
+    kb = b.volume(xyz, sc.pose)
+    E = np.uint64(0xFFFFFFFFFFFFFFFF)
+    assert np.all(kb <= ka)
+    assert np.all(kb[ka != E] != E)
+    extra = (kb != E) & (ka == E)
+    assert extra.sum() > 5 * (ka != E).sum()
+    s = (kb[extra] & np.uint64(0xFFFF)).astype(np.uint16).view(np.int16)
+    assert np.mean(s == spec.tau_u) > 0.9  # mostly truncated free space
+    assert np.all(s > -spec.tau_u)
+    a.close()
+    b.close()
+
+
+def test_voxel_sdf_wide_numerators():
+    """The distance numerator (q - c) . D of a voxel near the sensor of a
+    long ray exceeds 64 bits; the result is still the exact rounded,
+    clamped quotient (Python integers)."""
+    g = np.random.default_rng(77)
+    for _ in range(300):
+        o = [int(v) for v in g.integers(-2 ** 30 + 1, -2 ** 29, size=3)]
+        q = [int(v) for v in g.integers(2 ** 29, 2 ** 30, size=3)]
+        D = [q[a] - o[a] for a in range(3)]
+        r = brute.isqrt_floor(sum(d * d for d in D))
+        tau = int(g.integers(1, 32768))
+        # voxels near the sensor, near the point and at a random place
+        t = float(g.uniform(0, 1))
+        for base in (o, q, [int(o[a] + t * D[a]) for a in range(3)]):
+            gv = [(base[a] >> 10) + int(g.integers(-2, 3)) for a in range(3)]
+            dot = sum((q[a] - (1024 * gv[a] + 512)) * D[a] for a in range(3))
+            want = max(-tau, min(tau, brute.round_half_away(Fraction(dot, r))))
+            assert oracle.voxel_sdf(q, D, r, gv, tau) == want
+    # the sign of a huge numerator decides the clamp
+    assert oracle.voxel_sdf(q, D, r, [v >> 10 for v in o], 5) == 5
+
+
+def test_carve_and_interpolation_exclusive():
+    m = oracle.OracleMap((8, 8, 8), (0, 0, 0), 0.1, 3072, 64)
+    m.set_carving(True)
+    with pytest.raises(ValueError):
+        m.set_interpolation(30.0, 16)
+    m.set_carving(False)
+    m.set_interpolation(30.0, 16)
+    with pytest.raises(ValueError):
+        m.set_carving(True)
+    m.close()
