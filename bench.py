@@ -181,6 +181,41 @@ def interp_leg(torch, synth, TsdfMap, n_scans: int = 10, reps: int = 5):
             "algorithmic_GBps": B * reps / gpu_s / 1e9, "hbm_frac": B * reps / gpu_s / 1e9 / HBM_PEAK_GBS}
 
 
+def carve_leg(torch, synth, TsdfMap, n_scans: int = 50, reps: int = 3):
+    """Free-space carving on the config-2 sequence (every ray also walked
+    from the sensor to its band; sensors outside the window for the first
+    and last scans), one call per scan on the map's stream, timed with HIP
+    events on that stream."""
+    w = synth.config2(n_scans)
+    spec = w.maps[0]
+    dev = [torch.from_numpy(sc.xyz).to("cuda") for sc in w.scans]
+    st = torch.cuda.Stream()
+    m = TsdfMap.from_spec(spec, stream=st)
+    m.set_carving(True)
+    stats = [m.integrate(x, sc.pose, stats=True) for x, sc in zip(dev, w.scans)]
+    upd = sum(x["voxels_updated"] for x in stats)
+    visits = sum(x["visits"] for x in stats)
+    pts = sum(x["points_in"] for x in stats)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    st.synchronize()
+    e0.record(st)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for x, sc in zip(dev, w.scans):
+            m.integrate(x, sc.pose)
+    e1.record(st)
+    st.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = e0.elapsed_time(e1) * 1e-3
+    m.close()
+    n = reps * n_scans
+    B = 12.0 * pts + 128.0 * n_scans + 8.0 * upd  # per pass over the scans
+    return {"scans": n_scans, "visits_per_scan": visits / n_scans, "voxel_updates_per_scan": upd / n_scans,
+            "scans_per_s": n / wall, "voxel_updates_per_s": upd * reps / wall, "visits_per_s": visits * reps / gpu_s,
+            "gpu_ms_per_scan": 1e3 * gpu_s / n, "algorithmic_GBps": B * reps / gpu_s / 1e9,
+            "hbm_frac": B * reps / gpu_s / 1e9 / HBM_PEAK_GBS}
+
+
 def uneven_batch_leg(torch, synth, reps: int = 3):
     """Config 4: 256 scans of uneven shapes (16x512 .. 128x2048) into 16 maps
     of 256^3 at 8 cm, scan i into map i mod 16. Three forms on the same
@@ -311,6 +346,9 @@ def main():
     ap.add_argument("--no-interp", action="store_true", help="skip the vertical interpolation leg")
     ap.add_argument("--interp-only", action="store_true",
                     help="with --profile-only: the interpolating path on 10 config-2 scans only")
+    ap.add_argument("--no-carve", action="store_true", help="skip the free-space carving leg")
+    ap.add_argument("--carve-only", action="store_true",
+                    help="with --profile-only: the carving path on the config-2 sequence only")
     ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--profile-only", action="store_true", help="warmup + timed steps only (for rocprofv3)")
     ap.add_argument("--plain-only", action="store_true", help="with --profile-only: per-scan calls only")
@@ -343,6 +381,9 @@ def main():
     torch.cuda.set_device(0)
     if args.profile_only and args.interp_only:
         log(f"profile-only: interpolation {interp_leg(torch, synth, TsdfMap, reps=max(1, args.steps // 4))}")
+        return
+    if args.profile_only and args.carve_only:
+        log(f"profile-only: carving {carve_leg(torch, synth, TsdfMap, reps=max(1, args.steps // 10))}")
         return
     log("generating config-2 scans")
     w = synth.config2(args.scans)
@@ -490,6 +531,10 @@ def main():
     if not args.no_interp:
         log("vertical interpolation")
         interp = interp_leg(torch, synth, TsdfMap)
+    carve = None
+    if not args.no_carve:
+        log("free-space carving")
+        carve = carve_leg(torch, synth, TsdfMap)
     uneven = None
     if not args.no_uneven:
         log("uneven batches (config 4)")
@@ -557,6 +602,7 @@ def main():
         "shift": shift,
         "mesh": mesh,
         "registration": registration,
+        "carving": carve,
         "uneven_batches": uneven,
         "interpolation": interp,
         "serving": serving,

@@ -196,7 +196,8 @@ tsdf_status tsdf_profile_enable(tsdf_map *m, int32_t on);
  * filled voxels of band voxel centre c are the floor-set of [c - e, c + e],
  * each receiving the band voxel's key; the per-scan minimum decides as for
  * the band. Rays with r >= 2^30 are not filled. vfov_deg = 0 turns it off;
- * vfov_deg / hlines must be below 45 degrees (else TSDF_EINVAL). The first
+ * vfov_deg / hlines must be below 45 degrees, and carving must be off
+ * (else TSDF_EINVAL). The first
  * call that turns it on allocates an 8-byte key per voxel of the window
  * (TSDF_ENOMEM if that fails). Interpolating maps take their own
  * integration path (one thread per ray, 64-bit atomicMin on the key
@@ -206,6 +207,24 @@ tsdf_status tsdf_profile_enable(tsdf_map *m, int32_t on);
 tsdf_status tsdf_map_set_interpolation(tsdf_map *m, double vfov_deg, int32_t hlines);
 /* delta_z in 1/2^20 units, 0 when off. */
 tsdf_status tsdf_map_get_interpolation(const tsdf_map *m, int64_t *delta_q20);
+
+/* Free-space carving (a variant of the traversal: the ray traversed from the
+ * sensor position p towards the scan point, Sec. VI), for the map's following
+ * scans, on = 1 (0: off). Each ray longer than tau (r > tau) also walks the
+ * segment [o, S] from the sensor to the start of its band; its voxels take
+ * the ray's key exactly as band voxels do (s = clamp(rdiv((q - c) . D, r),
+ * +-tau), mostly the truncated +tau), and the per-scan minimum and the merge
+ * (Eq. (1), Eq. (2)) are unchanged. The band itself is unchanged; visits
+ * count both segments, so the voxel where they meet counts twice. Any ray
+ * the fixed point allows is walked exactly (|q|, |o| < 2^30). Not together
+ * with vertical interpolation: TSDF_EINVAL when interpolation is on (and
+ * tsdf_map_set_interpolation fails while carving is on). Carving maps take
+ * the key-volume path described above (the first call that turns it on
+ * allocates the 8-byte key per voxel; TSDF_ENOMEM if that fails), also in
+ * tsdf_integrate_batch. */
+tsdf_status tsdf_map_set_carving(tsdf_map *m, int32_t on);
+/* 1 when carving is on, else 0. */
+tsdf_status tsdf_map_get_carving(const tsdf_map *m, int32_t *on);
 
 /* Point-to-TSDF registration (the paper's stated next step, Sec. VIII;
  * HATSDF localises directly in its TSDF, Sec. I). A scan point p lands at

@@ -109,14 +109,17 @@ hipError_t launch_batch(const BatchArrays &B, const LaunchCaps &caps, hipStream_
                         hipEvent_t ev_binned, hipEvent_t ev_tiles);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
 
-// One scan with vertical interpolation between scan lines (interp.hip).
+// One scan through the global key volume (interp.hip): with vertical
+// interpolation between scan lines (dq > 0), or with free-space carving.
 struct InterpScan {
     RayParams rp;
     const float *xyz;  // device points
     int64_t n;
-    int64_t dq;        // delta_z of Eq. (3) in 1/2^20 units
+    int64_t dq;        // delta_z of Eq. (3) in 1/2^20 units (0 with carving)
     int64_t up[3];     // the sensor's up vector in 1/1024 units
+    int32_t carve;     // walk each ray longer than tau from the sensor as well
     int32_t origin[3], dims[3];
+    int32_t ring0[3];  // floor_mod(origin, dims): the slot of the window's first voxel
     int16_t *sdf, *w;
     int32_t w_max;
     unsigned long long *keys;      // [nx*ny*nz] per-scan keys, all EMPTY between scans

@@ -15,6 +15,13 @@
 // wave per run, merges the keys of touched runs (Eq. (1), Eq. (2)) and
 // empties them again.
 //
+// Free-space carving uses the same key volume and merge: a ray longer than
+// tau also walks [o, S] from the sensor to the start of its band (the long
+// walk, clipped to the window), whose voxels take the ray's key like band
+// voxels. The first rays to reach a voxel near the sensor settle its key, so
+// a visit reads the key first and issues the atomic only when it would lower
+// it (keys only fall during a scan, so a stale read at worst costs an atomic).
+//
 // Integer ranges (all exact): d = rdiv(1024 D, r) has |d| <= 1026, the up
 // vector U is in 1/1024 units, so |int| < 2^31 and int . int < 2^62; a fill
 // applies to rays of r < 2^30 (|D|^2 < 2^62); h is capped at 65535 (64
@@ -132,6 +139,47 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
     block_add(visits, &P.counters[1]);
 }
 
+__global__ __launch_bounds__(kInterpBlock) void k_carve_scan(InterpScan P)
+{
+    const int64_t i = (int64_t)blockIdx.x * kInterpBlock + threadIdx.x;
+    uint64_t valid = 0, visits = 0;
+    int32_t q[3];
+    Ray R;
+    if (i < P.n && quantise(P.xyz[3 * i], P.xyz[3 * i + 1], P.xyz[3 * i + 2], P.rp, q) && make_ray(q, P.rp, R)) {
+        valid = 1;
+        int32_t lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = P.origin[a];
+            hi[a] = P.origin[a] + P.dims[a];
+        }
+        // g inside the window: slot_a = floor_mod(g_a, dims_a)
+        auto visit = [&](const int32_t g[3], uint64_t key) {
+            int64_t sl = 0;
+            for (int a = 0; a < 3; ++a) {
+                int32_t v = g[a] - P.origin[a] + P.ring0[a];
+                v -= v >= P.dims[a] ? P.dims[a] : 0;
+                sl = sl * P.dims[a] + v;
+            }
+            unsigned long long *k = &P.keys[sl];
+            if (*k > key) {
+                atomicMin(k, (unsigned long long)key);
+                P.touched[sl >> 6] = 1;
+            }
+            ++visits;
+        };
+        if (R.r > (double)P.rp.tau) carve_free_segment(R, P.rp, (uint32_t)i, lo, hi, visit);
+        Walk W;
+        walk_init(R, W);
+        do {
+            bool inside = true;
+            for (int a = 0; a < 3; ++a) inside = inside && W.g[a] >= lo[a] && W.g[a] < hi[a];
+            if (inside) visit(W.g, pack_key(voxel_sdf(W.n, R, P.rp.tau), (uint32_t)i));
+        } while (walk_next(W));
+    }
+    block_add(valid, &P.counters[0]);
+    block_add(visits, &P.counters[1]);
+}
+
 // One wave per run of 64 slots; runs never touched this scan are skipped
 // after reading their byte.
 __global__ __launch_bounds__(256) void k_interp_merge(InterpScan P, int64_t nvox)
@@ -163,7 +211,10 @@ hipError_t launch_interp(const InterpScan &P, int64_t nvox, hipStream_t stream)
 {
     if (P.n > 0) {
         const int64_t blocks = (P.n + kInterpBlock - 1) / kInterpBlock;
-        hipLaunchKernelGGL(k_interp_scan, dim3((uint32_t)blocks), dim3(kInterpBlock), 0, stream, P);
+        if (P.carve)
+            hipLaunchKernelGGL(k_carve_scan, dim3((uint32_t)blocks), dim3(kInterpBlock), 0, stream, P);
+        else
+            hipLaunchKernelGGL(k_interp_scan, dim3((uint32_t)blocks), dim3(kInterpBlock), 0, stream, P);
     }
     int64_t mblocks = (nvox + 255) / 256;  // four runs of 64 slots per block
     if (mblocks > 8192) mblocks = 8192;

@@ -377,4 +377,188 @@ __device__ __forceinline__ bool box_walk_next(BoxWalk &V)
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// Long walk: the exact voxel set of a segment [A, B] of any length the fixed
+// point allows (|L_a| = |B_a - A_a| < 2^31), clipped to a box of voxels
+// [lo, hi). Free-space carving walks the ray from the sensor with it, a
+// segment far too long for the products of the band walk above.
+//
+// With T_a the next crossing time of axis a scaled by |L_a| (an integer at
+// most |L_a| + 1024), two axes are ordered by
+//   C_ab = 2 (T_a |L_b| - T_b |L_a|) + (dec_a - dec_b),
+// dec = 1 on a decreasing axis: C_ab <= 0 when a's crossing comes first or
+// at the same time and of the same type (both step), C_ab >= 0 the other way
+// round, so the walk's order (time, then increasing before decreasing) needs
+// no division. While both axes still cross, their next crossings lie within
+// one cell time (1024 / |L|) of the current time, so |C_ab| <= 2048
+// max(|L_a|, |L_b|) + 1 < 2^43, and a step of axis a adds the exact integer
+// 2048 |L_b|: exact in float64. Setting the walk down inside the box takes
+// 64-bit integer products below 2^62.2.
+// ---------------------------------------------------------------------------
+struct LongWalk {
+    int32_t g[3];
+    int32_t step[3];
+    int32_t rem[3];   // crossings still ahead on each axis (to the segment's end, or to leaving the box)
+    int32_t xit;      // bit a: the last of axis a's rem crossings leaves the box
+    double C01, C02, C12;
+    double K[3];      // 2048 |L_a|
+};
+
+// floor(a / b) for 0 <= a < 2^63, 0 < b < 2^42: a float64 estimate, then one
+// exact correction each way (the quotient is below 2^22, so the estimate is
+// within one of it).
+__device__ __forceinline__ int64_t floor_div_i64(int64_t a, int64_t b)
+{
+    int64_t k = (int64_t)((double)a / (double)b);
+    k -= k * b > a ? 1 : 0;
+    k += (k + 1) * b <= a ? 1 : 0;
+    return k;
+}
+
+// Set the walk down on the first voxel of [A, B] inside [lo, hi), with c[a]
+// the crossings taken on each axis to get there; false when no voxel of the
+// segment lies in the box. Coordinates are monotone along the walk, so the
+// voxels inside the box form one run: it starts after the event at which the
+// last axis enters the box's range (every crossing at or before that event in
+// the walk's order is taken) and ends at the first event that leaves it.
+__device__ __forceinline__ bool long_walk_init(const int32_t A[3], const int32_t B[3], const int32_t lo[3],
+                                               const int32_t hi[3], LongWalk &W, int32_t c[3])
+{
+    int64_t absL[3], T0[3];
+    int32_t g0[3], N[3], kin[3], X[3];
+    bool dec[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int64_t L = (int64_t)B[a] - A[a];
+        absL[a] = L < 0 ? -L : L;
+        dec[a] = L < 0;
+        g0[a] = A[a] >> 10;  // arithmetic shift: floor division
+        const int32_t gB = B[a] >> 10;
+        W.step[a] = L > 0 ? 1 : (L < 0 ? -1 : 0);
+        N[a] = gB > g0[a] ? gB - g0[a] : g0[a] - gB;
+        // scaled time of the first crossing: the distance to the next face
+        T0[a] = L >= 0 ? (int64_t)(g0[a] + 1) * 1024 - A[a] : (int64_t)A[a] - (int64_t)g0[a] * 1024;
+        // crossing counts at which this axis is inside [lo, hi): kin <= k < X
+        if (L > 0) {
+            kin[a] = lo[a] - g0[a] > 0 ? lo[a] - g0[a] : 0;
+            X[a] = hi[a] - g0[a];
+        } else if (L < 0) {
+            kin[a] = g0[a] - (hi[a] - 1) > 0 ? g0[a] - (hi[a] - 1) : 0;
+            X[a] = g0[a] - lo[a] + 1;
+        } else {
+            if (g0[a] < lo[a] || g0[a] >= hi[a]) return false;
+            kin[a] = 0;
+            X[a] = 0x7fffffff;
+        }
+        if (X[a] <= 0 || kin[a] > N[a]) return false;
+    }
+    // the entry event: the latest of the axes' entering crossings
+    int e = -1;
+    int64_t Te = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (kin[a] == 0) continue;
+        const int64_t Ta = T0[a] + 1024 * (int64_t)(kin[a] - 1);
+        if (e >= 0) {
+            const int64_t d = Ta * absL[e] - Te * absL[a];
+            if (d < 0 || (d == 0 && !(dec[a] && !dec[e]))) continue;  // not after the current latest
+        }
+        e = a;
+        Te = Ta;
+    }
+    int64_t T[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        int64_t k = 0;
+        if (e == b) {
+            k = kin[b];
+        } else if (e >= 0 && N[b] > 0) {
+            // crossings j of b with T0_b + 1024 j scaled by |L_e| at or before
+            // Te scaled by |L_b|: 1024 j |L_e| <= num (< num if b decreases
+            // and the entry crossing increases: b's crossing comes after it)
+            const int64_t num = Te * absL[b] - T0[b] * absL[e];
+            const int64_t den = 1024 * absL[e];
+            if (!(dec[b] && !dec[e]))
+                k = num < 0 ? 0 : floor_div_i64(num, den) + 1;
+            else
+                k = num <= 0 ? 0 : floor_div_i64(num - 1, den) + 1;
+            k = k < N[b] ? k : N[b];
+        }
+        if (k >= X[b]) return false;  // left the box before it entered on another axis
+        c[b] = (int32_t)k;
+        W.g[b] = g0[b] + W.step[b] * (int32_t)k;
+        W.rem[b] = (N[b] < X[b] ? N[b] : X[b]) - (int32_t)k;
+        T[b] = T0[b] + 1024 * k;
+        W.K[b] = 2048.0 * (double)absL[b];
+    }
+    W.xit = (X[0] <= N[0] ? 1 : 0) | (X[1] <= N[1] ? 2 : 0) | (X[2] <= N[2] ? 4 : 0);
+    // int64 differences below 2^62.2 (live pairs: below 2^42)
+    W.C01 = 2.0 * (double)(T[0] * absL[1] - T[1] * absL[0]) + (double)((int)dec[0] - (int)dec[1]);
+    W.C02 = 2.0 * (double)(T[0] * absL[2] - T[2] * absL[0]) + (double)((int)dec[0] - (int)dec[2]);
+    W.C12 = 2.0 * (double)(T[1] * absL[2] - T[2] * absL[1]) + (double)((int)dec[1] - (int)dec[2]);
+    return true;
+}
+
+// Next voxel: the axes that step (bit a for axis a), 0 when the segment ends
+// or the walk leaves the box.
+__device__ __forceinline__ int long_walk_next(LongWalk &W)
+{
+    const bool l0 = W.rem[0] > 0, l1 = W.rem[1] > 0, l2 = W.rem[2] > 0;
+    const bool s0 = l0 && (!l1 || W.C01 <= 0.0) && (!l2 || W.C02 <= 0.0);
+    const bool s1 = l1 && (!l0 || W.C01 >= 0.0) && (!l2 || W.C12 <= 0.0);
+    const bool s2 = l2 && (!l0 || W.C02 >= 0.0) && (!l1 || W.C12 >= 0.0);
+    const int m = (s0 ? 1 : 0) | (s1 ? 2 : 0) | (s2 ? 4 : 0);
+    int last = (W.rem[0] == 1 ? 1 : 0) | (W.rem[1] == 1 ? 2 : 0) | (W.rem[2] == 1 ? 4 : 0);
+    if (m & last & W.xit) return 0;  // this event leaves the box
+    W.g[0] += s0 ? W.step[0] : 0;
+    W.g[1] += s1 ? W.step[1] : 0;
+    W.g[2] += s2 ? W.step[2] : 0;
+    W.rem[0] -= s0 ? 1 : 0;
+    W.rem[1] -= s1 ? 1 : 0;
+    W.rem[2] -= s2 ? 1 : 0;
+    W.C01 += (s0 ? W.K[1] : 0.0) - (s1 ? W.K[0] : 0.0);
+    W.C02 += (s0 ? W.K[2] : 0.0) - (s2 ? W.K[0] : 0.0);
+    W.C12 += (s1 ? W.K[2] : 0.0) - (s2 ? W.K[1] : 0.0);
+    return m;
+}
+
+// The free-space segment [o, S] of a ray longer than tau (free-space
+// carving), clipped to the box [lo, hi): visit(g, key) for each of its voxels
+// in the box, in walk order. The distance numerator n = (q - c) . D falls by
+// 1024 |D_a| at every step on axis a (each axis moves the way D points), from
+// up to about 3 * 2^62 near the sensor to above -2^42 at S. It is carried
+// modulo 2^64 as u = n - H + 2^50, H = tau r - floor(r / 2) the smallest n
+// whose distance rounds to tau or more: u never wraps, u >= 2^50 means s =
+// +tau without any division, and below that n = u - 2^50 + H is exact in
+// float64 (|n| < 2^47).
+template <class Visit>
+__device__ __forceinline__ void carve_free_segment(const Ray &R, const RayParams &P, uint32_t i, const int32_t lo[3],
+                                                   const int32_t hi[3], Visit &&visit)
+{
+    LongWalk W;
+    int32_t c[3];
+    if (!long_walk_init(P.o, R.S, lo, hi, W, c)) return;
+    constexpr uint64_t kBias = 1ull << 50;
+    const int64_t r = (int64_t)R.r;
+    const int64_t H = (int64_t)P.tau * r - (r >> 1);
+    uint64_t u = kBias - (uint64_t)H;
+    uint64_t du[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int64_t Da = (int64_t)R.D[a];
+        u += (uint64_t)(((int64_t)R.q[a] - 1024 * (int64_t)W.g[a] - 512) * Da);
+        du[a] = (uint64_t)(1024 * (Da < 0 ? -Da : Da));
+    }
+    const double Hd = (double)H;
+    const uint64_t key_far = pack_key(P.tau, i);
+    for (;;) {
+        uint64_t key = key_far;
+        if (u < kBias) key = pack_key(voxel_sdf((double)(int64_t)(u - kBias) + Hd, R, P.tau), i);
+        visit(W.g, key);
+        const int m = long_walk_next(W);
+        if (!m) break;
+        u -= ((m & 1) ? du[0] : 0) + ((m & 2) ? du[1] : 0) + ((m & 4) ? du[2] : 0);
+    }
+}
+
 }  // namespace tsdf

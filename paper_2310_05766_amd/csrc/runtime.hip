@@ -26,8 +26,10 @@ struct tsdf_map {
     int32_t lt[3] = {0, 0, 0};  // integration tiling; {0, 0, 0}: chosen per call
     int32_t tile_grid = 0;      // 0: as many workgroups as fit the device
     std::unique_ptr<Engine> engine;  // single-scan integration on the map's stream
-    // vertical interpolation between scan lines (its own path, interp.hip)
+    // vertical interpolation between scan lines, or free-space carving (their
+    // own path through a key volume over the window, interp.hip)
     int64_t interp_dq = 0;                     // delta_z of Eq. (3), 1/2^20 units; 0: off
+    bool carve = false;                        // rays longer than tau walked from the sensor
     unsigned long long *interp_keys = nullptr;  // [nvox], EMPTY between scans
     uint8_t *interp_touched = nullptr;          // [ceil(nvox / 64)], 0 between scans
     unsigned long long *interp_ctr = nullptr;   // device counters (3)
@@ -532,7 +534,10 @@ tsdf_status tsdf_map_destroy(tsdf_map *m)
     return TSDF_OK;
 }
 
-// One scan through the interpolating path, on the map's stream.
+// Whether the map's scans take the key-volume path (interp.hip).
+static bool keyvol_path(const tsdf_map *m) { return m->interp_dq > 0 || m->carve; }
+
+// One scan through the key-volume path, on the map's stream.
 static tsdf_status integrate_interp(tsdf_map *m, const float *xyz, int64_t n, bool host, const double pose[16],
                              tsdf_scan_stats *stats)
 {
@@ -548,10 +553,13 @@ static tsdf_status integrate_interp(tsdf_map *m, const float *xyz, int64_t n, bo
         P.up[a] = (int64_t)nearbyint(pose[4 * a + 2] * 1024.0);
         P.origin[a] = m->d.origin[a];
         P.dims[a] = m->d.dims[a];
+        const int32_t r0 = m->d.origin[a] % m->d.dims[a];
+        P.ring0[a] = r0 < 0 ? r0 + m->d.dims[a] : r0;
     }
     P.rp.tau = m->d.tau_q10;
     P.n = n;
     P.dq = m->interp_dq;
+    P.carve = m->carve ? 1 : 0;
     P.sdf = m->sdf;
     P.w = m->w;
     P.w_max = m->d.w_max;
@@ -588,6 +596,36 @@ static tsdf_status integrate_interp(tsdf_map *m, const float *xyz, int64_t n, bo
     return TSDF_OK;
 }
 
+// The key volume (all EMPTY), its touched-run bytes and counters, once.
+static tsdf_status ensure_key_volume(tsdf_map *m)
+{
+    if (m->interp_keys) return TSDF_OK;
+    if (hipMalloc(&m->interp_keys, (size_t)m->nvox * sizeof(unsigned long long)) != hipSuccess) {
+        m->interp_keys = nullptr;
+        return TSDF_ENOMEM;
+    }
+    const int64_t runs = (m->nvox + 63) / 64;
+    const size_t touched_bytes = (size_t)((runs + 3) / 4 * 4);
+    if (hipMalloc(&m->interp_ctr, 4 * sizeof(unsigned long long)) != hipSuccess) m->interp_ctr = nullptr;
+    if (hipHostMalloc(&m->interp_ctr_host, 4 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+        m->interp_ctr_host = nullptr;
+    if (hipMalloc(&m->interp_touched, touched_bytes) != hipSuccess) m->interp_touched = nullptr;
+    if (!m->interp_ctr || !m->interp_ctr_host || !m->interp_touched) {
+        if (m->interp_ctr) (void)hipFree(m->interp_ctr);
+        if (m->interp_ctr_host) (void)hipHostFree(m->interp_ctr_host);
+        if (m->interp_touched) (void)hipFree(m->interp_touched);
+        (void)hipFree(m->interp_keys);
+        m->interp_ctr = nullptr;
+        m->interp_ctr_host = nullptr;
+        m->interp_touched = nullptr;
+        m->interp_keys = nullptr;
+        return TSDF_ENOMEM;
+    }
+    HIPCHK(m, launch_fill_u32((uint32_t *)m->interp_keys, m->nvox * 2, 0xffffffffu, m->stream));
+    HIPCHK(m, launch_fill_u32((uint32_t *)m->interp_touched, (int64_t)(touched_bytes / 4), 0u, m->stream));
+    return TSDF_OK;
+}
+
 tsdf_status tsdf_map_set_interpolation(tsdf_map *m, double vfov_deg, int32_t hlines)
 {
     if (!m) return TSDF_EINVAL;
@@ -602,22 +640,10 @@ tsdf_status tsdf_map_set_interpolation(tsdf_map *m, double vfov_deg, int32_t hli
     Guard g(m);
     if (!g.ok) return TSDF_EBUSY;
     if (m->poisoned) return TSDF_EDEVICE;
-    if (dq > 0 && !m->interp_keys) {
-        if (hipMalloc(&m->interp_keys, (size_t)m->nvox * sizeof(unsigned long long)) != hipSuccess) {
-            m->interp_keys = nullptr;
-            return TSDF_ENOMEM;
-        }
-        const int64_t runs = (m->nvox + 63) / 64;
-        const size_t touched_bytes = (size_t)((runs + 3) / 4 * 4);
-        if (hipMalloc(&m->interp_ctr, 4 * sizeof(unsigned long long)) != hipSuccess ||
-            hipHostMalloc(&m->interp_ctr_host, 4 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
-            hipMalloc(&m->interp_touched, touched_bytes) != hipSuccess) {
-            (void)hipFree(m->interp_keys);
-            m->interp_keys = nullptr;
-            return TSDF_ENOMEM;
-        }
-        HIPCHK(m, launch_fill_u32((uint32_t *)m->interp_keys, m->nvox * 2, 0xffffffffu, m->stream));
-        HIPCHK(m, launch_fill_u32((uint32_t *)m->interp_touched, (int64_t)(touched_bytes / 4), 0u, m->stream));
+    if (dq > 0 && m->carve) return TSDF_EINVAL;  // not together with carving
+    if (dq > 0) {
+        const tsdf_status st = ensure_key_volume(m);
+        if (st != TSDF_OK) return st;
     }
     m->interp_dq = dq;
     return TSDF_OK;
@@ -862,6 +888,28 @@ tsdf_status tsdf_map_get_interpolation(const tsdf_map *m, int64_t *delta_q20)
     return TSDF_OK;
 }
 
+tsdf_status tsdf_map_set_carving(tsdf_map *m, int32_t on)
+{
+    if (!m || (on != 0 && on != 1)) return TSDF_EINVAL;
+    Guard g(m);
+    if (!g.ok) return TSDF_EBUSY;
+    if (m->poisoned) return TSDF_EDEVICE;
+    if (on && m->interp_dq > 0) return TSDF_EINVAL;  // not together with interpolation
+    if (on) {
+        const tsdf_status st = ensure_key_volume(m);
+        if (st != TSDF_OK) return st;
+    }
+    m->carve = on != 0;
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_map_get_carving(const tsdf_map *m, int32_t *on)
+{
+    if (!m || !on) return TSDF_EINVAL;
+    *on = m->carve ? 1 : 0;
+    return TSDF_OK;
+}
+
 tsdf_status tsdf_integrate_scan(tsdf_map *m, const float *xyz, int64_t n_points, tsdf_ptr_kind kind,
                                 const double pose[16], tsdf_scan_stats *stats)
 {
@@ -870,7 +918,7 @@ tsdf_status tsdf_integrate_scan(tsdf_map *m, const float *xyz, int64_t n_points,
     Guard g(m);
     if (!g.ok) return TSDF_EBUSY;
     if (m->poisoned) return TSDF_EDEVICE;
-    if (m->interp_dq > 0) return integrate_interp(m, xyz, n_points, kind == TSDF_PTR_HOST, pose, stats);
+    if (keyvol_path(m)) return integrate_interp(m, xyz, n_points, kind == TSDF_PTR_HOST, pose, stats);
     std::vector<MapRef> maps{map_ref(m)};
     std::vector<ScanRef> scans{ScanRef{0, xyz, n_points, kind == TSDF_PTR_HOST, pose}};
     tsdf_status st = m->engine->run(maps, scans, tiling_for(m, false), m->tile_grid, stats);
@@ -884,14 +932,14 @@ tsdf_status tsdf_integrate_batch(const tsdf_scan_desc *scans, int32_t count, tsd
     if (count < 0 || (count > 0 && !scans)) return TSDF_EINVAL;
     if (kind != TSDF_PTR_HOST && kind != TSDF_PTR_DEVICE) return TSDF_EINVAL;
     if (count == 0) return TSDF_OK;
-    // Scans of maps with vertical interpolation take their own path, one by
+    // Scans of maps with vertical interpolation or carving take their own path, one by
     // one in order on their map's stream, between events on the batch
     // stream; the others go through the batched engine as one batch. (Maps
     // are independent, so the two groups may run in either order.)
     bool any_interp = false;
     for (int32_t k = 0; k < count; ++k) {
         if (!scans[k].map) return TSDF_EINVAL;
-        any_interp = any_interp || scans[k].map->interp_dq > 0;
+        any_interp = any_interp || keyvol_path(scans[k].map);
     }
     if (any_interp) {
         hipStream_t bs = hip_stream ? (hipStream_t)hip_stream : scans[0].map->stream;
@@ -899,7 +947,7 @@ tsdf_status tsdf_integrate_batch(const tsdf_scan_desc *scans, int32_t count, tsd
         std::vector<int32_t> rest_at;
         for (int32_t k = 0; k < count; ++k) {
             tsdf_map *m = scans[k].map;
-            if (m->interp_dq <= 0) {
+            if (!keyvol_path(m)) {
                 rest.push_back(scans[k]);
                 rest_at.push_back(k);
                 continue;

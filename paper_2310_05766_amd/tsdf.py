@@ -215,6 +215,17 @@ class TsdfMap:
         check(_abi.lib().tsdf_map_get_interpolation(self._h, C.byref(d)), "tsdf_map_get_interpolation")
         return int(d.value)
 
+    def set_carving(self, on: bool = True) -> bool:
+        """Free-space carving for the following scans: each ray longer than
+        tau is also walked from the sensor to the start of its band."""
+        check(_abi.lib().tsdf_map_set_carving(self._h, 1 if on else 0), "tsdf_map_set_carving")
+        return self.get_carving()
+
+    def get_carving(self) -> bool:
+        v = C.c_int32()
+        check(_abi.lib().tsdf_map_get_carving(self._h, C.byref(v)), "tsdf_map_get_carving")
+        return bool(v.value)
+
     def set_tiling(self, log2_tile, workgroups: int = 0):
         """Candidate-buffer tiling (2^log2_tile voxels per axis); results do not depend on it."""
         lt = (C.c_int32 * 3)(*[int(v) for v in log2_tile])
