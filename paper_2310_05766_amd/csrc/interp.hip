@@ -18,9 +18,13 @@
 // Free-space carving uses the same key volume and merge: a ray longer than
 // tau also walks [o, S] from the sensor to the start of its band (the long
 // walk, clipped to the window), whose voxels take the ray's key like band
-// voxels. The first rays to reach a voxel near the sensor settle its key, so
-// a visit reads the key first and issues the atomic only when it would lower
-// it (keys only fall during a scan, so a stale read at worst costs an atomic).
+// voxels.
+//
+// A carving visit reads the key first and issues the atomic only when it
+// would lower it (keys only fall during a scan, so a stale read at worst
+// costs an atomic), and marks the run only when it read EMPTY: the path is
+// bound by how many scattered 64-bit atomics and stores the L2 takes per
+// second.
 //
 // Integer ranges (all exact): d = rdiv(1024 D, r) has |d| <= 1026, the up
 // vector U is in 1/1024 units, so |int| < 2^31 and int . int < 2^62; a fill
@@ -139,41 +143,80 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
     block_add(visits, &P.counters[1]);
 }
 
+// Slot of a window voxel: floor_mod(g_a, dims_a) per axis, z fastest.
+__device__ __forceinline__ int64_t window_slot(const InterpScan &P, const int32_t g[3])
+{
+    int64_t sl = 0;
+    for (int a = 0; a < 3; ++a) {
+        int32_t v = g[a] - P.origin[a] + P.ring0[a];
+        v -= v >= P.dims[a] ? P.dims[a] : 0;
+        sl = sl * P.dims[a] + v;
+    }
+    return sl;
+}
+
+// One candidate: the atomic only when it would lower the key read, the
+// run's mark only by a thread that read EMPTY (the first atomic on a slot in
+// a scan comes from such a thread: no key can be read before one is written).
+__device__ __forceinline__ void offer_key(const InterpScan &P, int64_t sl, uint64_t key)
+{
+    unsigned long long *k = &P.keys[sl];
+    const unsigned long long seen = *k;
+    if (seen > key) {
+        atomicMin(k, (unsigned long long)key);
+        if (seen == kEmptyKey) P.touched[sl >> 6] = 1;
+    }
+}
+
+// Free-space walks of neighbouring points (consecutive indices: neighbouring
+// columns of one scan line) that start in the same voxel visit the voxels
+// they share at the same step, so the wave walks in lockstep and a lane
+// whose left neighbour holds the same slot with a smaller key leaves the
+// candidate to it (that neighbour offers it, or is covered the same way by
+// a smaller key further left). A lane whose walk has ended still shows the
+// last candidate it held, which was offered.
 __global__ __launch_bounds__(kInterpBlock) void k_carve_scan(InterpScan P)
 {
     const int64_t i = (int64_t)blockIdx.x * kInterpBlock + threadIdx.x;
+    const int lane = (int)(threadIdx.x & 63u);
     uint64_t valid = 0, visits = 0;
     int32_t q[3];
     Ray R;
-    if (i < P.n && quantise(P.xyz[3 * i], P.xyz[3 * i + 1], P.xyz[3 * i + 2], P.rp, q) && make_ray(q, P.rp, R)) {
-        valid = 1;
-        int32_t lo[3], hi[3];
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = P.origin[a];
-            hi[a] = P.origin[a] + P.dims[a];
+    int32_t lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = P.origin[a];
+        hi[a] = P.origin[a] + P.dims[a];
+    }
+    const bool ray = i < P.n && quantise(P.xyz[3 * i], P.xyz[3 * i + 1], P.xyz[3 * i + 2], P.rp, q) &&
+                     make_ray(q, P.rp, R);
+    FreeWalk F;
+    bool act = ray && R.r > (double)P.rp.tau && free_walk_init(R, P.rp, lo, hi, F);
+    int64_t sl = -1;
+    uint64_t key = 0;
+    while (__any(act)) {
+        if (act) {
+            sl = window_slot(P, F.W.g);
+            key = free_walk_key(F, R, P.rp.tau, (uint32_t)i);
         }
-        // g inside the window: slot_a = floor_mod(g_a, dims_a)
-        auto visit = [&](const int32_t g[3], uint64_t key) {
-            int64_t sl = 0;
-            for (int a = 0; a < 3; ++a) {
-                int32_t v = g[a] - P.origin[a] + P.ring0[a];
-                v -= v >= P.dims[a] ? P.dims[a] : 0;
-                sl = sl * P.dims[a] + v;
-            }
-            unsigned long long *k = &P.keys[sl];
-            if (*k > key) {
-                atomicMin(k, (unsigned long long)key);
-                P.touched[sl >> 6] = 1;
-            }
+        const int64_t left_sl = __shfl_up(sl, 1);
+        const uint64_t left_key = __shfl_up(key, 1);
+        if (act) {
+            if (!(lane > 0 && left_sl == sl && left_key <= key)) offer_key(P, sl, key);
             ++visits;
-        };
-        if (R.r > (double)P.rp.tau) carve_free_segment(R, P.rp, (uint32_t)i, lo, hi, visit);
+            act = free_walk_next(F);
+        }
+    }
+    if (ray) {
+        valid = 1;
         Walk W;
         walk_init(R, W);
         do {
             bool inside = true;
             for (int a = 0; a < 3; ++a) inside = inside && W.g[a] >= lo[a] && W.g[a] < hi[a];
-            if (inside) visit(W.g, pack_key(voxel_sdf(W.n, R, P.rp.tau), (uint32_t)i));
+            if (inside) {
+                offer_key(P, window_slot(P, W.g), pack_key(voxel_sdf(W.n, R, P.rp.tau), (uint32_t)i));
+                ++visits;
+            }
         } while (walk_next(W));
     }
     block_add(valid, &P.counters[0]);

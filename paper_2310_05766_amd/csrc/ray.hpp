@@ -523,42 +523,53 @@ __device__ __forceinline__ int long_walk_next(LongWalk &W)
 }
 
 // The free-space segment [o, S] of a ray longer than tau (free-space
-// carving), clipped to the box [lo, hi): visit(g, key) for each of its voxels
-// in the box, in walk order. The distance numerator n = (q - c) . D falls by
+// carving), clipped to the box [lo, hi), walked voxel by voxel with the key
+// each voxel receives. The distance numerator n = (q - c) . D falls by
 // 1024 |D_a| at every step on axis a (each axis moves the way D points), from
 // up to about 3 * 2^62 near the sensor to above -2^42 at S. It is carried
 // modulo 2^64 as u = n - H + 2^50, H = tau r - floor(r / 2) the smallest n
 // whose distance rounds to tau or more: u never wraps, u >= 2^50 means s =
 // +tau without any division, and below that n = u - 2^50 + H is exact in
 // float64 (|n| < 2^47).
-template <class Visit>
-__device__ __forceinline__ void carve_free_segment(const Ray &R, const RayParams &P, uint32_t i, const int32_t lo[3],
-                                                   const int32_t hi[3], Visit &&visit)
-{
+struct FreeWalk {
     LongWalk W;
+    uint64_t u, du[3];
+    double Hd;
+};
+constexpr uint64_t kFreeBias = 1ull << 50;
+
+// false when no voxel of the segment lies in the box.
+__device__ __forceinline__ bool free_walk_init(const Ray &R, const RayParams &P, const int32_t lo[3],
+                                               const int32_t hi[3], FreeWalk &F)
+{
     int32_t c[3];
-    if (!long_walk_init(P.o, R.S, lo, hi, W, c)) return;
-    constexpr uint64_t kBias = 1ull << 50;
+    if (!long_walk_init(P.o, R.S, lo, hi, F.W, c)) return false;
     const int64_t r = (int64_t)R.r;
     const int64_t H = (int64_t)P.tau * r - (r >> 1);
-    uint64_t u = kBias - (uint64_t)H;
-    uint64_t du[3];
+    F.u = kFreeBias - (uint64_t)H;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int64_t Da = (int64_t)R.D[a];
-        u += (uint64_t)(((int64_t)R.q[a] - 1024 * (int64_t)W.g[a] - 512) * Da);
-        du[a] = (uint64_t)(1024 * (Da < 0 ? -Da : Da));
+        F.u += (uint64_t)(((int64_t)R.q[a] - 1024 * (int64_t)F.W.g[a] - 512) * Da);
+        F.du[a] = (uint64_t)(1024 * (Da < 0 ? -Da : Da));
     }
-    const double Hd = (double)H;
-    const uint64_t key_far = pack_key(P.tau, i);
-    for (;;) {
-        uint64_t key = key_far;
-        if (u < kBias) key = pack_key(voxel_sdf((double)(int64_t)(u - kBias) + Hd, R, P.tau), i);
-        visit(W.g, key);
-        const int m = long_walk_next(W);
-        if (!m) break;
-        u -= ((m & 1) ? du[0] : 0) + ((m & 2) ? du[1] : 0) + ((m & 4) ? du[2] : 0);
-    }
+    F.Hd = (double)H;
+    return true;
+}
+
+// Key of the current voxel for point i.
+__device__ __forceinline__ uint64_t free_walk_key(const FreeWalk &F, const Ray &R, int32_t tau, uint32_t i)
+{
+    const int32_t s = F.u >= kFreeBias ? tau : voxel_sdf((double)(int64_t)(F.u - kFreeBias) + F.Hd, R, tau);
+    return pack_key(s, i);
+}
+
+// Next voxel; false when the segment ends or leaves the box.
+__device__ __forceinline__ bool free_walk_next(FreeWalk &F)
+{
+    const int m = long_walk_next(F.W);
+    F.u -= ((m & 1) ? F.du[0] : 0) + ((m & 2) ? F.du[1] : 0) + ((m & 4) ? F.du[2] : 0);
+    return m != 0;
 }
 
 }  // namespace tsdf
