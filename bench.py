@@ -145,6 +145,23 @@ def shift_leg(torch, TsdfMap, synth):
             "host_link_GBps": moved / t / 1e9}
 
 
+ATOMIC_BOUND = "scattered 64-bit atomicMin, tsdf_atomic_probe: 2048 waves x 64 lanes x 128 atomics"
+
+
+def atomic_rates(torch, n_keys: int, stream) -> dict:
+    """Scattered 64-bit atomicMin per second on a key volume of n_keys (the
+    bound of the key-volume paths), and on an L2-resident 4 MiB."""
+    from paper_2310_05766_amd.tsdf import atomic_probe
+    keys = torch.empty(n_keys, dtype=torch.int64, device="cuda")
+    out = {}
+    for pattern, name in ((0, "window_key_volume"), (1, "l2_resident_4MiB")):
+        atomic_probe(keys, 2048, 16, pattern, stream=stream)  # warm
+        ms = min(atomic_probe(keys, 2048, 128, pattern, stream=stream) for _ in range(3))
+        out[name] = 2048 * 64 * 128 / (ms * 1e-3)
+    del keys
+    return out
+
+
 def interp_leg(torch, synth, TsdfMap, n_scans: int = 10, reps: int = 5):
     """Vertical interpolation between scan lines (45 deg over 128 lines, the
     OS1-128's) on the first scans of the config-2 sequence, one call per
@@ -175,10 +192,15 @@ def interp_leg(torch, synth, TsdfMap, n_scans: int = 10, reps: int = 5):
     m.close()
     n = reps * n_scans
     B = 12.0 * pts + 128.0 * n_scans + 8.0 * upd  # per pass over the scans
+    probe = atomic_rates(torch, spec.n_voxels, st)
+    vps = visits * reps / gpu_s
     return {"scans": n_scans, "delta_z_q20": dq, "visits_per_scan": visits / n_scans,
             "voxel_updates_per_scan": upd / n_scans, "scans_per_s": n / wall,
-            "voxel_updates_per_s": upd * reps / wall, "gpu_ms_per_scan": 1e3 * gpu_s / n,
-            "algorithmic_GBps": B * reps / gpu_s / 1e9, "hbm_frac": B * reps / gpu_s / 1e9 / HBM_PEAK_GBS}
+            "voxel_updates_per_s": upd * reps / wall, "visits_per_s": vps, "gpu_ms_per_scan": 1e3 * gpu_s / n,
+            "algorithmic_GBps": B * reps / gpu_s / 1e9, "hbm_frac": B * reps / gpu_s / 1e9 / HBM_PEAK_GBS,
+            "atomic_roofline": {"bound": ATOMIC_BOUND, "atomics_per_s": probe, "visits_per_s": vps,
+                                "frac": vps / probe["window_key_volume"],
+                                "note": "one atomic per visit"}}
 
 
 def carve_leg(torch, synth, TsdfMap, n_scans: int = 50, reps: int = 3):
@@ -210,10 +232,15 @@ def carve_leg(torch, synth, TsdfMap, n_scans: int = 50, reps: int = 3):
     m.close()
     n = reps * n_scans
     B = 12.0 * pts + 128.0 * n_scans + 8.0 * upd  # per pass over the scans
+    probe = atomic_rates(torch, spec.n_voxels, st)
+    vps = visits * reps / gpu_s
     return {"scans": n_scans, "visits_per_scan": visits / n_scans, "voxel_updates_per_scan": upd / n_scans,
-            "scans_per_s": n / wall, "voxel_updates_per_s": upd * reps / wall, "visits_per_s": visits * reps / gpu_s,
+            "scans_per_s": n / wall, "voxel_updates_per_s": upd * reps / wall, "visits_per_s": vps,
             "gpu_ms_per_scan": 1e3 * gpu_s / n, "algorithmic_GBps": B * reps / gpu_s / 1e9,
-            "hbm_frac": B * reps / gpu_s / 1e9 / HBM_PEAK_GBS}
+            "hbm_frac": B * reps / gpu_s / 1e9 / HBM_PEAK_GBS,
+            "atomic_roofline": {"bound": ATOMIC_BOUND, "atomics_per_s": probe, "visits_per_s": vps,
+                                "frac": vps / probe["window_key_volume"],
+                                "note": "a visit issues at most one atomic; the lockstep check leaves fewer"}}
 
 
 def uneven_batch_leg(torch, synth, reps: int = 3):

@@ -305,3 +305,16 @@ def batch_profile_read(stream, stage: str):
     check(_abi.lib().tsdf_batch_profile_read(_stream_handle(stream), BATCH_STAGES[stage], C.byref(ms), C.byref(n)),
           "tsdf_batch_profile_read")
     return float(ms.value), int(n.value)
+
+
+def atomic_probe(keys, waves: int = 2048, per_lane: int = 128, pattern: int = 0, stream=None) -> float:
+    """Milliseconds for waves * 64 * per_lane scattered 64-bit atomicMins on
+    the int64 device tensor keys (overwritten); pattern 1 keeps them in its
+    first 4 MiB. A measurement aid for the key-volume paths."""
+    import torch
+    if not (isinstance(keys, torch.Tensor) and keys.is_cuda and keys.dtype == torch.int64 and keys.is_contiguous()):
+        raise TypeError("keys must be a contiguous int64 CUDA tensor")
+    ms = C.c_float()
+    check(_abi.lib().tsdf_atomic_probe(C.c_void_p(keys.data_ptr()), keys.numel(), int(waves), int(per_lane),
+                                       int(pattern), _stream_handle(stream), C.byref(ms)), "tsdf_atomic_probe")
+    return float(ms.value)

@@ -188,3 +188,22 @@ def test_carving_arguments():
     assert gm.get_interpolation() == 0
     assert gm.set_carving(False) is False
     gm.close()
+
+
+def test_atomic_probe():
+    """The measurement aid behind the key-volume roofline: it applies
+    atomicMins inside the buffer (pattern 1 only to its first 2^19 keys) and
+    checks its arguments."""
+    import torch
+    from paper_2310_05766_amd import TsdfError
+    from paper_2310_05766_amd.tsdf import atomic_probe
+    keys = torch.full((1 << 20,), -1, dtype=torch.int64, device="cuda")
+    assert atomic_probe(keys, 64, 8, 1) > 0
+    torch.cuda.synchronize()
+    assert int((keys[: 1 << 19] != -1).sum()) > 0 and int((keys[1 << 19:] != -1).sum()) == 0
+    assert atomic_probe(keys, 64, 8, 0) > 0
+    torch.cuda.synchronize()
+    assert int((keys[1 << 19:] != -1).sum()) > 0
+    for args in [(keys[:1000], 64, 8, 1), (keys, 63, 8, 0), (keys, 64, 0, 0), (keys, 64, 8, 2)]:
+        with pytest.raises(TsdfError):
+            atomic_probe(*args)
