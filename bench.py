@@ -68,6 +68,33 @@ def read_traffic(kernel: str, workload_tag: str):
         return None
 
 
+# VALU issue capacity: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD
+# every 4 cycles (16 lanes per cycle), at 2.4 GHz
+VALU_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
+
+
+def read_valu_insts(kernel: str, workload_tag: str):
+    """SQ_INSTS_VALU per dispatch (wave instructions) from the committed
+    rocprofv3 counter summary, or None when it is missing or was taken on
+    other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"sq_counters_{workload_tag}.txt")
+    if not os.path.exists(path):
+        return None
+    lines = open(path).read().splitlines()
+    if not any(line.strip() == f"kernel sources sha256[:16]: {sources_digest()}" for line in lines):
+        return None
+    head = next((line for line in lines if line.startswith("| kernel |")), None)
+    row = next((line for line in lines if line.startswith(f"| `{kernel}` |")), None)
+    if head is None or row is None:
+        return None
+    cols = [c.strip() for c in head.strip("|").split("|")]
+    vals = [c.strip() for c in row.strip("|").split("|")]
+    try:
+        return float(vals[cols.index("SQ_INSTS_VALU")])
+    except (ValueError, IndexError):
+        return None
+
+
 def cpu_baseline(workload, max_seconds: float):
     """The oracle, single-threaded, on the first scans of the same sequence
     until max_seconds of integrate time have been spent."""
@@ -576,6 +603,12 @@ def main():
         cpu = cpu_baseline(w, args.cpu_seconds)
 
     value = U_step * args.steps / dt
+    valu_insts = read_valu_insts("k_tile", "config2_batch")
+    valu_issue = None
+    if valu_insts is not None:
+        t_tile = kt["k_tile"]["avg_us"] * 1e-6
+        valu_issue = {"wave_insts_per_launch": valu_insts, "peak_wave_insts_per_s": VALU_WAVE_INSTS_PER_S,
+                      "busy_frac": valu_insts / t_tile / VALU_WAVE_INSTS_PER_S}
     line = {
         "metric": METRIC,
         "value": value,
@@ -619,6 +652,9 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "algorithmic_bytes_per_launch": B_tile,
+            # what does bound it: VALU issue (committed SQ counters of the
+            # same kernel sources, over the live launch time)
+            "valu_issue": valu_issue,
         },
         "step_roofline": {
             "algorithmic_bytes": B_batch,
