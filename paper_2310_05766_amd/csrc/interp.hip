@@ -12,7 +12,7 @@
 // resolves keys with 64-bit atomicMin on a key volume over the window (8
 // bytes per voxel, all EMPTY between scans) and marks the key's run of 64
 // slots as touched (one byte per run, a plain store); a second kernel, one
-// wave per run, merges the keys of touched runs (Eq. (1), Eq. (2)) and
+// wave per 64 runs, merges the keys of touched runs (Eq. (1), Eq. (2)) and
 // empties them again.
 //
 // Free-space carving uses the same key volume and merge: a ray longer than
@@ -223,27 +223,43 @@ __global__ __launch_bounds__(kInterpBlock) void k_carve_scan(InterpScan P)
     block_add(visits, &P.counters[1]);
 }
 
-// One wave per run of 64 slots; runs never touched this scan are skipped
-// after reading their byte.
+// One wave per group of 64 runs of 64 slots: the wave reads the group's 64
+// touched bytes at once and clears them, then merges the touched runs one
+// after the other, each run's keys read before the previous run is written
+// back (a run's keys, then its voxels: two dependent reads per run).
 __global__ __launch_bounds__(256) void k_interp_merge(InterpScan P, int64_t nvox)
 {
     uint64_t updated = 0;
     const int64_t nruns = (nvox + 63) / 64;
+    const int64_t ngroups = (nruns + 63) / 64;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t waves = (int64_t)gridDim.x * blockDim.x / 64;
     const int lane = (int)(threadIdx.x & 63u);
-    for (int64_t b = wave; b < nruns; b += waves) {
-        if (!P.touched[b]) continue;  // the same for the whole wave
-        const int64_t j = b * 64 + lane;
-        if (j < nvox) {
-            const unsigned long long key = P.keys[j];
+    for (int64_t gi = wave; gi < ngroups; gi += waves) {
+        const int64_t b0 = gi * 64;
+        const bool t = b0 + lane < nruns && P.touched[b0 + lane] != 0;
+        if (t) P.touched[b0 + lane] = 0;
+        uint64_t mask = __ballot(t);  // the same for the whole wave
+        if (!mask) continue;
+        int64_t j = (b0 + __builtin_ctzll(mask)) * 64 + lane;
+        unsigned long long key = j < nvox ? P.keys[j] : kEmptyKey;
+        for (;;) {
+            mask &= mask - 1;
+            int64_t jn = 0;
+            unsigned long long keyn = kEmptyKey;
+            if (mask) {
+                jn = (b0 + __builtin_ctzll(mask)) * 64 + lane;
+                if (jn < nvox) keyn = P.keys[jn];
+            }
             if (key != kEmptyKey) {
                 merge_key(P.sdf[j], P.w[j], key, P.w_max);
                 P.keys[j] = kEmptyKey;
                 ++updated;
             }
+            if (!mask) break;
+            j = jn;
+            key = keyn;
         }
-        if (lane == 0) P.touched[b] = 0;
     }
     block_add(updated, &P.counters[2]);
 }
@@ -259,7 +275,8 @@ hipError_t launch_interp(const InterpScan &P, int64_t nvox, hipStream_t stream)
         else
             hipLaunchKernelGGL(k_interp_scan, dim3((uint32_t)blocks), dim3(kInterpBlock), 0, stream, P);
     }
-    int64_t mblocks = (nvox + 255) / 256;  // four runs of 64 slots per block
+    // four waves per block, one group of 64 runs per wave
+    int64_t mblocks = ((nvox + 63) / 64 + 255) / 256;
     if (mblocks > 8192) mblocks = 8192;
     hipLaunchKernelGGL(k_interp_merge, dim3((uint32_t)(mblocks > 0 ? mblocks : 1)), dim3(256), 0, stream, P, nvox);
     return hipGetLastError();
