@@ -292,21 +292,6 @@ __global__ __launch_bounds__(kAllocBlock) void k_alloc(BatchArrays B)
     }
 }
 
-// rdiv(n, d) for 1 <= d <= 2^15 and |n| <= 2^15 d (Eq. (1): n = g w + v,
-// d = w + 1 with |g|, |v| <= tau < 2^15): float64 estimate of
-// floor((2|n| + d) / 2d) from the reciprocal, which is within one of it (the
-// quotient is at most 2^15), then one exact correction each way (every
-// product is an integer below 2^53).
-__device__ __forceinline__ int32_t rdiv_small(int32_t n, int32_t d)
-{
-    const double dd = 2.0 * (double)d;
-    const double a = 2.0 * fabs((double)n) + (double)d;
-    double k = floor(a * approx_rcp(dd));
-    k -= k * dd > a ? 1.0 : 0.0;
-    k += __fma_rn(k, dd, dd) <= a ? 1.0 : 0.0;
-    return n < 0 ? -(int32_t)k : (int32_t)k;
-}
-
 // Eq. (1) with one unit of weight, Eq. (2).
 __device__ __forceinline__ void merge_one(int16_t &sdf, int16_t &w, uint64_t key, int32_t w_max)
 {

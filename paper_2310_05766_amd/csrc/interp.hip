@@ -39,18 +39,41 @@ namespace {
 
 constexpr int kInterpBlock = 256;
 
-// rdiv(n, d) for d > 0: to nearest, ties away from zero (64-bit integers).
-__device__ __forceinline__ int64_t rdiv64(int64_t n, int64_t d)
+// rdiv(n, d) = sign(n) floor((2|n| + d) / 2d), to nearest with ties away
+// from zero, for a divisor 0 < d < 2^32 fixed per ray (given as 2d and
+// 1 / 2d correctly rounded) and |n| < 2^61 with a quotient below 2^31: the
+// float64 estimate is within one of the quotient, and one exact 64-bit
+// correction each way fixes it (no integer division). Here: d = r < 2^30
+// with n = 1024 D_a or (c - o) . D, and d = |int| < 2^31 with n = h int_a.
+__device__ __forceinline__ int64_t rdiv_by(int64_t n, uint64_t d2, double inv_d2)
 {
     const uint64_t a = (uint64_t)(n < 0 ? -n : n);
-    const uint64_t k = (2 * a + (uint64_t)d) / (2 * (uint64_t)d);
+    const uint64_t num = 2 * a + (d2 >> 1);
+    uint64_t k = (uint64_t)((double)num * inv_d2);
+    k -= k * d2 > num ? 1u : 0u;
+    k += (k + 1) * d2 <= num ? 1u : 0u;
     return n < 0 ? -(int64_t)k : (int64_t)k;
 }
 
-__device__ __forceinline__ int64_t floor_mod64(int64_t a, int64_t b)
+// rdiv(n, 2^20) for |n| < 2^62: a shift.
+__device__ __forceinline__ int64_t rdiv_2p20(int64_t n)
 {
-    const int64_t m = a % b;
-    return m < 0 ? m + b : m;
+    const uint64_t a = (uint64_t)(n < 0 ? -n : n);
+    const int64_t k = (int64_t)((2 * a + (1u << 20)) >> 21);
+    return n < 0 ? -k : k;
+}
+
+// Slot of a voxel inside the window: floor_mod(g_a, dims_a) per axis, z
+// fastest.
+__device__ __forceinline__ int64_t window_slot(const InterpScan &P, const int32_t g[3])
+{
+    int64_t sl = 0;
+    for (int a = 0; a < 3; ++a) {
+        int32_t v = g[a] - P.origin[a] + P.ring0[a];
+        v -= v >= P.dims[a] ? P.dims[a] : 0;
+        sl = sl * P.dims[a] + v;
+    }
+    return sl;
 }
 
 // Eq. (1) with one unit of weight, Eq. (2) (|g w + v| <= tau (w + 1)).
@@ -58,7 +81,7 @@ __device__ __forceinline__ void merge_key(int16_t &sdf, int16_t &w, uint64_t key
 {
     const int64_t v = (int16_t)(uint16_t)(key & 0xffffu);
     const int64_t gw = w, gv = sdf;
-    sdf = (int16_t)rdiv64(gv * gw + v, gw + 1);
+    sdf = (int16_t)rdiv_small((int32_t)(gv * gw + v), (int32_t)(gw + 1));
     w = (int16_t)(gw + 1 < w_max ? gw + 1 : w_max);
 }
 
@@ -84,10 +107,14 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
         int64_t Di[3], v[3] = {0, 0, 0}, nv = 0, dd = 0;
         for (int a = 0; a < 3; ++a) Di[a] = (int64_t)R.D[a];
         const bool fills = P.dq > 0 && rr < ((int64_t)1 << 30);
+        const uint64_t r2 = 2 * (uint64_t)rr;
+        const double inv_r2 = 1.0 / (double)r2;
+        uint64_t nv2 = 0;
+        double inv_nv2 = 0.0;
         if (fills) {
             int64_t d[3], w[3];
             for (int a = 0; a < 3; ++a) {
-                d[a] = rdiv64(1024 * Di[a], rr);
+                d[a] = rdiv_by(1024 * Di[a], r2, inv_r2);
                 dd += Di[a] * Di[a];
             }
             w[0] = d[1] * P.up[2] - d[2] * P.up[1];
@@ -97,6 +124,8 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
             v[1] = d[2] * w[0] - d[0] * w[2];
             v[2] = d[0] * w[1] - d[1] * w[0];
             nv = (int64_t)isqrt_u64((uint64_t)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+            nv2 = 2 * (uint64_t)nv;
+            inv_nv2 = nv > 0 ? 1.0 / (double)nv2 : 0.0;
         }
         Walk W;
         walk_init(R, W);
@@ -107,11 +136,11 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
             int64_t e[3] = {0, 0, 0};
             if (fills && nv > 0) {
                 // (c - o) . D = (q - o) . D - (q - c) . D, the walk's n
-                const int64_t len = rdiv64(dd - (int64_t)W.n, rr);
+                const int64_t len = rdiv_by(dd - (int64_t)W.n, r2, inv_r2);
                 if (len > 0) {
-                    int64_t h = rdiv64(P.dq * len, (int64_t)1 << 20);
+                    int64_t h = rdiv_2p20(P.dq * len);
                     h = h < 65535 ? h : 65535;
-                    for (int a = 0; a < 3; ++a) e[a] = rdiv64(h * v[a], nv);
+                    for (int a = 0; a < 3; ++a) e[a] = rdiv_by(h * v[a], nv2, inv_nv2);
                 }
             }
             Ray F;  // a segment only: the fill walk needs no distances
@@ -129,9 +158,7 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
                 for (int a = 0; a < 3; ++a)
                     inside = inside && FW.g[a] >= P.origin[a] && FW.g[a] < P.origin[a] + P.dims[a];
                 if (inside) {
-                    const int64_t slot =
-                        (floor_mod64(FW.g[0], P.dims[0]) * P.dims[1] + floor_mod64(FW.g[1], P.dims[1])) * P.dims[2] +
-                        floor_mod64(FW.g[2], P.dims[2]);
+                    const int64_t slot = window_slot(P, FW.g);
                     atomicMin(&P.keys[slot], key);
                     P.touched[slot >> 6] = 1;
                     ++visits;
@@ -141,18 +168,6 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
     }
     block_add(valid, &P.counters[0]);
     block_add(visits, &P.counters[1]);
-}
-
-// Slot of a window voxel: floor_mod(g_a, dims_a) per axis, z fastest.
-__device__ __forceinline__ int64_t window_slot(const InterpScan &P, const int32_t g[3])
-{
-    int64_t sl = 0;
-    for (int a = 0; a < 3; ++a) {
-        int32_t v = g[a] - P.origin[a] + P.ring0[a];
-        v -= v >= P.dims[a] ? P.dims[a] : 0;
-        sl = sl * P.dims[a] + v;
-    }
-    return sl;
 }
 
 // One candidate: the atomic only when it would lower the key read, the

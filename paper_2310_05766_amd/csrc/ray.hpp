@@ -76,6 +76,21 @@ __device__ __forceinline__ double floor_div_exact(double a, double d, double inv
     return k;
 }
 
+// rdiv(n, d) for 1 <= d <= 2^15 and |n| <= 2^15 d (Eq. (1): n = g w + v,
+// d = w + 1 with |g|, |v| <= tau < 2^15): float64 estimate of
+// floor((2|n| + d) / 2d) from the reciprocal, which is within one of it (the
+// quotient is at most 2^15), then one exact correction each way (every
+// product is an integer below 2^53).
+__device__ __forceinline__ int32_t rdiv_small(int32_t n, int32_t d)
+{
+    const double dd = 2.0 * (double)d;
+    const double a = 2.0 * fabs((double)n) + (double)d;
+    double k = floor(a * approx_rcp(dd));
+    k -= k * dd > a ? 1.0 : 0.0;
+    k += __fma_rn(k, dd, dd) <= a ? 1.0 : 0.0;
+    return n < 0 ? -(int32_t)k : (int32_t)k;
+}
+
 // Rounded division to nearest, ties away from zero: sign(n) floor((2|n| + d) / 2d).
 __device__ __forceinline__ double rdiv_exact(double n, double d2, double inv_d2, double d, double cap)
 {
