@@ -1,9 +1,10 @@
 // Per-ray device arithmetic of the TSDF path (FeatSense, arXiv 2310.05766,
 // Sec. VI): world transform and fixed-point rounding of a scan point, the
 // truncation band around it, the exact voxel walk across the band, and the
-// signed distance each walked voxel receives.
+// signed distance each walked voxel receives; further down, the long walk of
+// free-space carving, whose ranges are stated with it.
 //
-// Every integer the walk and the distance need stays below 2^53 in
+// Every integer the band walk and the distance need stays below 2^53 in
 // magnitude, so it is carried in float64 registers, where adds, multiplies
 // and compares of such integers are exact and run at full rate on CDNA
 // (a 64-bit integer add costs two VALU ops, a float64 add one).
