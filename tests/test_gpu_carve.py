@@ -207,3 +207,38 @@ def test_atomic_probe():
     for args in [(keys[:1000], 64, 8, 1), (keys, 63, 8, 0), (keys, 64, 0, 0), (keys, 64, 8, 2)]:
         with pytest.raises(TsdfError):
             atomic_probe(*args)
+
+
+def test_carving_degenerate_cases():
+    """Empty and all-NaN scans, points at the sensor, rays no longer than
+    tau, axis-aligned rays from a sensor on a voxel corner (flat axes, ties
+    at t = 0), and a window one voxel thick."""
+    cases = [((16, 16, 16), (-8, -8, -8)), ((24, 1, 20), (-12, 0, -10)), ((1, 1, 40), (0, 0, -20))]
+    vs, tau = 0.1, 3072
+    for case, (dims, origin) in enumerate(cases):
+        om = oracle.OracleMap(dims, origin, vs, tau, 64)
+        gm = gpu_map(dims, origin, vs, tau, 64)
+        om.set_carving(True)
+        gm.set_carving(True)
+        corner = np.eye(4)  # sensor on a voxel corner of the grid
+        centre = np.eye(4)
+        centre[:3, 3] = [0.05, 0.05, 0.05]  # sensor on a voxel centre
+        axis = np.array([[d * s, 0, 0] for d in (0.35, 1.0, 2.2) for s in (1, -1)] +
+                        [[0, d * s, 0] for d in (0.35, 1.0, 2.2) for s in (1, -1)] +
+                        [[0, 0, d * s] for d in (0.35, 1.0, 2.2) for s in (1, -1)] +
+                        [[0.5, 0.5, 0.0], [-0.7, 0.7, 0.7], [0.3, 0.0, -0.9]], dtype=np.float32)
+        scans = [
+            (np.zeros((0, 3), np.float32), corner),
+            (np.full((50, 3), np.nan, np.float32), corner),
+            (np.zeros((20, 3), np.float32), centre),  # every point at the sensor
+            (synth.fuzz_scan((99, case), 400, extent_m=0.25, nan_frac=0.1), centre),  # r <= tau mostly
+            (axis, corner),
+            (axis, centre),
+            (synth.fuzz_scan((98, case), 600, extent_m=2.0, nan_frac=0.05, grid_snap=0.1), corner),
+        ]
+        for k, (xyz, pose) in enumerate(scans):
+            say("carving degenerate case", case, "scan", k)
+            assert gm.integrate(xyz, pose, stats=True) == om.integrate(xyz, pose), (case, k)
+        assert same(gm, om, dims)
+        gm.close()
+        om.close()
