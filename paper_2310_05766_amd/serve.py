@@ -51,13 +51,17 @@ class GpuExecutor:
         self.want_stats = stats
 
     @staticmethod
-    def map_bytes(spec) -> int:
-        return 4 * spec.n_voxels  # int16 sdf + int16 weight per voxel
+    def map_bytes(spec, options=None) -> int:
+        # int16 sdf + int16 weight per voxel; a map with carving or
+        # interpolation also holds an 8-byte key per voxel
+        return (12 if _key_volume(options) else 4) * spec.n_voxels
 
-    def create_map(self, spec, lane: int):
+    def create_map(self, spec, lane: int, options=None):
         from .tsdf import TsdfMap
 
-        return TsdfMap.from_spec(spec, stream=self.streams[lane])
+        m = TsdfMap.from_spec(spec, stream=self.streams[lane])
+        apply_options(m, options)
+        return m
 
     def launch(self, lane: int, items):
         """Enqueue [(map, xyz, pose), ...] on the lane; returns a token."""
@@ -89,12 +93,32 @@ class GpuExecutor:
             batch_release(st)
 
 
+def _key_volume(options) -> bool:
+    return bool(options) and (bool(options.get("carving")) or options.get("interpolation") is not None)
+
+
+def apply_options(m, options):
+    """Per-session map options: {"carving": True} or {"interpolation":
+    (vfov_deg, hlines)} (not both: the library rejects the pair)."""
+    if not options:
+        return
+    unknown = set(options) - {"carving", "interpolation"}
+    if unknown:
+        raise ValueError(f"unknown map options {sorted(unknown)}")
+    if options.get("interpolation") is not None:
+        vfov, lines = options["interpolation"]
+        m.set_interpolation(vfov, lines)
+    if options.get("carving"):
+        m.set_carving(True)
+
+
 @dataclass
 class _Session:
     sid: int
     spec: object
     lane: int
     bytes: int
+    options: object = None
     map: object = None
     queue: collections.deque = field(default_factory=collections.deque)  # (k, xyz, pose, record)
     inflight: int = 0
@@ -127,11 +151,13 @@ class Server:
         return self.clock() - self.t0
 
     # -- sessions ---------------------------------------------------------------
-    def open_session(self, sid: int, spec):
-        nb = self.ex.map_bytes(spec)
+    def open_session(self, sid: int, spec, options=None):
+        """options: per-session map options (apply_options); they count in
+        the session's memory."""
+        nb = self.ex.map_bytes(spec, options) if options else self.ex.map_bytes(spec)
         if nb > self.budget:
             raise ValueError(f"session {sid}: map of {nb} bytes exceeds the whole budget")
-        s = _Session(sid, spec, lane=sid % self.lanes, bytes=nb)
+        s = _Session(sid, spec, lane=sid % self.lanes, bytes=nb, options=options)
         self.sessions[sid] = s
         self.waiting.append(s)
         self._admit()
@@ -145,7 +171,8 @@ class Server:
             s = self.waiting.popleft()
             if s.closed:
                 continue
-            s.map = self.ex.create_map(s.spec, s.lane)
+            s.map = self.ex.create_map(s.spec, s.lane, s.options) if s.options else \
+                self.ex.create_map(s.spec, s.lane)
             self.used += s.bytes
             self.admit_log.append((self.now(), s.sid))
 
@@ -235,16 +262,18 @@ class Server:
 
 
 def replay(server: Server, sessions, scans_of, speedup: float = 1.0, close_at_end: bool = True):
-    """Replay an arrival trace: sessions = [(sid, spec, arrivals[])], and
-    scans_of(sid, k) -> (xyz, pose). Arrival times are divided by speedup.
-    Returns the completed records."""
+    """Replay an arrival trace: sessions = [(sid, spec, arrivals[])] or
+    [(sid, spec, arrivals[], options)], and scans_of(sid, k) -> (xyz, pose).
+    Arrival times are divided by speedup. Returns the completed records."""
     events = []
-    for sid, spec, arrivals in sessions:
-        server.open_session(sid, spec)
+    last_k = {}
+    for sess in sessions:
+        sid, spec, arrivals = sess[:3]
+        server.open_session(sid, spec, sess[3] if len(sess) > 3 else None)
+        last_k[sid] = len(arrivals) - 1
         for k, t in enumerate(arrivals):
             events.append((float(t) / speedup, sid, k))
     events.sort()
-    last_k = {sid: len(arr) - 1 for sid, _, arr in sessions}
     i = 0
     while i < len(events) or server.pending():
         now = server.now()

@@ -21,7 +21,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-def run(sessions, budget, speedup):
+def run(sessions, budget, speedup, options=None):
     from paper_2310_05766_amd.serve import GpuExecutor, Server, latency_summary, replay
     ex = GpuExecutor(lanes=2)
     maps = {}
@@ -43,7 +43,9 @@ def run(sessions, budget, speedup):
     for s in sessions:
         for k in range(len(s.arrivals)):
             scans_of(s.sid, k)
-    recs = replay(srv, [(s.sid, s.spec, s.arrivals) for s in sessions], scans_of, speedup=speedup)
+    options = options or {}
+    recs = replay(srv, [(s.sid, s.spec, s.arrivals, options.get(s.sid)) for s in sessions], scans_of,
+                  speedup=speedup)
     ex.close()
     return recs, maps, srv, latency_summary(recs)
 
@@ -83,4 +85,28 @@ def test_small_budget_admission(reference):
     assert max(t for t, _ in srv.admit_log) > 0.0  # someone waited for memory
     for s in sessions:
         ref = reference[s.sid]
+        assert np.array_equal(maps[s.sid][0], ref[0]) and np.array_equal(maps[s.sid][1], ref[1]), s.sid
+
+
+def test_sessions_with_map_options():
+    """A carving session and an interpolating session served beside a plain
+    one: each map bit-exact with the oracle integrating that session's scans
+    in order with the same option."""
+    import oracle
+    sessions = synth.config5(n_sessions=3, duration_s=1.0)
+    opts = {0: {"carving": True}, 1: {"interpolation": (30.0, 16)}, 2: None}
+    recs, maps, srv, lat = run(sessions, budget=200 * 10 ** 9, speedup=4.0, options=opts)
+    say("options mix:", lat, "batches", srv.batches)
+    for s in sessions:
+        m = oracle.OracleMap.from_spec(s.spec)
+        if s.sid == 0:
+            m.set_carving(True)
+        if s.sid == 1:
+            m.set_interpolation(30.0, 16)
+        for k in range(len(s.arrivals)):
+            sc = s.scan(k)
+            m.integrate(sc.xyz, sc.pose)
+        o = s.spec.origin
+        ref = m.readback(o, tuple(o[a] + s.spec.dims[a] for a in range(3)))
+        m.close()
         assert np.array_equal(maps[s.sid][0], ref[0]) and np.array_equal(maps[s.sid][1], ref[1]), s.sid

@@ -18,11 +18,15 @@ class OracleExecutor:
         self.launches = []
 
     @staticmethod
-    def map_bytes(spec):
-        return 4 * spec.n_voxels
+    def map_bytes(spec, options=None):
+        from paper_2310_05766_amd.serve import GpuExecutor
+        return GpuExecutor.map_bytes(spec, options)
 
-    def create_map(self, spec, lane):
-        return oracle.OracleMap.from_spec(spec)
+    def create_map(self, spec, lane, options=None):
+        from paper_2310_05766_amd.serve import apply_options
+        m = oracle.OracleMap.from_spec(spec)
+        apply_options(m, options)
+        return m
 
     def launch(self, lane, items):
         self.launches.append((lane, len(items)))
@@ -144,3 +148,39 @@ def test_replay_trace_time_compressed():
     for sid, sp, _ in sessions:
         ks = [r.k for r in recs if r.sid == sid]
         assert ks == sorted(ks)
+
+
+def test_session_options_and_their_memory():
+    """Carving and interpolation sessions next to plain ones: each map equals
+    its scans integrated alone with the same option, and an option's key
+    volume counts in the session's memory (8 more bytes per voxel)."""
+    ex = OracleExecutor()
+    sp = small_spec(0)
+    opts = {0: {"carving": True}, 1: {"interpolation": (30.0, 8)}, 2: None}
+    plain, keyed = OracleExecutor.map_bytes(sp), OracleExecutor.map_bytes(sp, {"carving": True})
+    assert keyed == 3 * plain
+    srv = Server(ex, budget_bytes=keyed + plain + 10, lanes=2, max_batch=4)
+    sessions = [(sid, sp, np.sort(np.random.default_rng(sid + 40).uniform(0, 0.2, size=4)), opts[sid])
+                for sid in range(3)]
+    maps = {}
+    srv.on_release = lambda sid, m: maps.__setitem__(sid, window(m, sp))
+    recs = replay(srv, sessions, scan, speedup=4.0)
+    assert len(recs) == 12
+    # session 1's key volume does not fit beside session 0's: it (and the
+    # plain session queued behind it) waits until session 0 has finished
+    assert [s for _, s in srv.admit_log] == [0, 1, 2]
+    last0 = max(r.done for r in recs if r.sid == 0)
+    assert srv.admit_log[1][0] >= last0
+    for sid in range(3):
+        ref = oracle.OracleMap.from_spec(sp)
+        if opts[sid] and opts[sid].get("carving"):
+            ref.set_carving(True)
+        if opts[sid] and opts[sid].get("interpolation"):
+            ref.set_interpolation(*opts[sid]["interpolation"])
+        for k in range(4):
+            ref.integrate(*scan(sid, k))
+        b = window(ref, sp)
+        assert np.array_equal(maps[sid][0], b[0]) and np.array_equal(maps[sid][1], b[1]), sid
+    from paper_2310_05766_amd.serve import apply_options
+    with pytest.raises(ValueError):
+        apply_options(oracle.OracleMap.from_spec(sp), {"carve": True})
