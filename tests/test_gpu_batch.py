@@ -198,3 +198,35 @@ def test_autotuner_candidates_agree(tmp_path, monkeypatch):
     assert tuple(best["lt"]) in [tuple(c["lt"]) for c in best["candidates"]]
     again = autotune(spec, sample, mode="batch", reps=1)
     assert again["cached"] and tuple(again["lt"]) == tuple(best["lt"])
+
+
+@pytest.mark.parametrize("lt", [(2, 2, 5), (3, 3, 6), (4, 4, 4), (0, 0, 0)])
+def test_longest_bands_resume_at_tile_entries(lt):
+    """tau = 32767 (a band of 64 voxels) on rays along z that enter a tile
+    after 64 or more voxel crossings on z: the resume counts of the tile
+    pass reach their largest values (up to 66 per axis)."""
+    from paper_2310_05766_amd.tsdf import integrate_batch
+    vs, tau = 1.0, 32767
+    dims, origin = (8, 8, 256), (-4, -4, 0)
+    om = oracle.OracleMap(dims, origin, vs, tau, 64)
+    gm = gpu_map(dims, origin, vs, tau, 64)
+    gm.set_tiling(lt)
+    pose = np.eye(4)
+    pose[:3, 3] = [0.5, 0.5, 0.5]  # sensor on a voxel centre
+    pts = []
+    for k, zk in enumerate((1, 2, 3, 4, 5)):
+        for dz in (2, 10, 500, 1000, 1023):
+            # band start S_z = 1024 * 32 * zk + dz (fixed point): 64 crossings
+            qz = 1024 * 32 * zk + dz + tau
+            pts.append([0.0, 0.0, (qz - 512) / 1024.0])
+            pts.append([0.25 * (k - 2) / 1024.0, 0.0, (qz - 512 + 1) / 1024.0])  # nearly vertical
+    xyz = np.array(pts, dtype=np.float32)
+    assert gm.integrate(xyz, pose, stats=True) == om.integrate(xyz, pose)
+    poses = [pose.copy() for _ in range(3)]
+    for j, p in enumerate(poses):
+        p[:3, 3] = [0.5 - j, 0.5 + j, 0.5 + 7 * j]
+    st = integrate_batch([(gm, xyz, p) for p in poses], stats=True)
+    assert st == [om.integrate(xyz, p) for p in poses]
+    assert same(gm, om, dims)
+    gm.close()
+    om.close()
