@@ -130,3 +130,28 @@ def test_interpolation_arguments():
     assert gm.set_interpolation(45.0, 128) == oracle.interp_delta(45.0, 128)
     assert gm.set_interpolation(0.0, 0) == 0
     gm.close()
+
+
+def test_interpolation_with_far_sensors():
+    """Sensors 2^18 to 2^20 voxels from the points (r up to about 2^30 in
+    fixed point): the fill length along the ray and its divisions by r reach
+    their largest values, the fill height its cap of 64 voxels, and rays of
+    r >= 2^30 get no fill."""
+    vs = 0.05
+    dims, origin = (24, 24, 40), (1000, -12, -20)
+    om = oracle.OracleMap(dims, origin, vs, 3072, 64)
+    gm = gpu_map(dims, origin, vs, 3072, 64)
+    om.set_interpolation(40.0, 8)
+    gm.set_interpolation(40.0, 8)
+    centre = np.array([(origin[a] + dims[a] / 2) * vs for a in range(3)])
+    for k, far in enumerate((1 << 18, 1 << 19, (1 << 20) - 1100, (1 << 20) + 100)):
+        pose = np.eye(4)
+        pose[:3, 3] = centre - np.array([far * vs, 0.0, 0.0])
+        g = np.random.default_rng((97, k))
+        world = centre + g.uniform(-0.5, 0.5, size=(400, 3)) * np.array([1.0, 1.0, 1.5])
+        xyz = (world - pose[:3, 3]).astype(np.float32)
+        say("interpolation, sensor", far, "voxels away")
+        assert gm.integrate(xyz, pose, stats=True) == om.integrate(xyz, pose), k
+    assert same(gm, om, dims)
+    gm.close()
+    om.close()
