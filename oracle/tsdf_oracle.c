@@ -15,7 +15,9 @@
  *      rounded to global fixed point, 1/1024 of a voxel;
  *   2. the ray from the sensor position p to the point x is traversed across
  *      the truncation band around x (Sec. VI: voxels are filled while
- *      traversing the ray from p to x);
+ *      traversing the ray from p to x); as options, also from p to the start
+ *      of the band (free-space carving, the traversal read literally), or
+ *      with the vertical fill between scan lines (Sec. VI, Eq. (3), Eq. (4));
  *   3. per scan, each voxel keeps the smallest distance over all rays that
  *      reach it (Sec. VI: the per-scan volume V takes the smallest distance
  *      of all rays for each voxel);
@@ -609,7 +611,8 @@ int or_set_interpolation(omap *m, int64_t dq)
     return OR_OK;
 }
 
-/* Free-space carving for the following scans (on = 1): each ray longer than
+/* Free-space carving for the following scans (on = 1; Sec. VI, the ray
+ * traversed from the sensor position p to the point x): each ray longer than
  * tau also walks the segment [o, S] from the sensor position to the start
  * of its band, so the voxels in front of the surface receive their (mostly
  * truncated, +tau) distance as well; the band is unchanged. Not together
