@@ -405,6 +405,7 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
     __shared__ int32_t s_o[kMaxGroup][3], s_tau[kMaxGroup];
     __shared__ uint32_t s_vis[kMaxGroup], s_upd[kMaxGroup];
     __shared__ uint32_t s_busy, s_job;
+    __shared__ uint8_t s_list[kMaxSeq];  // the tile's busy sequence slots, in order
     const BatchHdr H = *B.hdr;
     const int32_t lsum = H.lt[0] + H.lt[1] + H.lt[2];
     const uint32_t tvox = 1u << lsum;
@@ -421,17 +422,23 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
     while (job < nne) {
         const uint32_t g = uniform(B.nonempty[job]);
         const int32_t mb = uniform((int32_t)B.nonempty_map[job]);
-        // the tile's runs, one load per sequence slot, all in flight together
+        // the tile's runs, one load per sequence slot, all in flight
+        // together; the first wave (at most 64 slots) lists the busy slots in
+        // order, so that groups of G hold busy slots only
+        uint32_t c = 0;
         if (threadIdx.x < (uint32_t)H.S) {
             const uint32_t k = threadIdx.x * H.gtiles + g;
-            const uint32_t c = B.counts[k];
+            c = B.counts[k];
             s_cnt[threadIdx.x] = c;
             s_beg[threadIdx.x] = c ? B.offsets[k] : 0u;
             s_scan[threadIdx.x] = c ? B.seq_scan[mb * H.S + threadIdx.x] : -1;
         }
-        if (threadIdx.x == 0) s_busy = 0;
+        if (threadIdx.x < 64u) {
+            const uint64_t bm = __ballot(c != 0u);
+            if (c) s_list[__popcll(bm & ((1ull << threadIdx.x) - 1ull))] = (uint8_t)threadIdx.x;
+            if (threadIdx.x == 0) s_busy = (uint32_t)__popcll(bm);
+        }
         __syncthreads();
-        if (threadIdx.x < (uint32_t)H.S && s_cnt[threadIdx.x]) atomicAdd(&s_busy, 1u);
         const MapDev MD = uniform_map(B.maps[mb]);
         const uint32_t t = g - MD.tile_base;
         const uint32_t tz = t % (uint32_t)MD.nt[2];
@@ -458,34 +465,33 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                 c_w[v] = MD.w[slot];
             }
         }
-        for (int sq0 = 0; sq0 < H.S; sq0 += G) {
-            const int ng = min(G, H.S - sq0);
+        const int nbusy = (int)uniform(s_busy);
+        for (int j0 = 0; j0 < nbusy; j0 += G) {
+            // a group: busy slots j0 .. j0 + ng - 1 of the list, in order
+            const int ng = min(G, nbusy - j0);
             uint32_t gsum = 0;
-            for (int r = 0; r < ng; ++r) gsum += s_cnt[sq0 + r];
+            for (int r = 0; r < ng; ++r) gsum += s_cnt[s_list[j0 + r]];
             gsum = uniform(gsum);
-            if (gsum == 0u) continue;  // same value for the whole workgroup
             if (threadIdx.x < (uint32_t)ng) {
                 const int r = (int)threadIdx.x;
                 s_vis[r] = 0;
                 s_upd[r] = 0;
-                if (s_cnt[sq0 + r]) {
-                    const ScanDev &SD = B.scans[s_scan[sq0 + r]];
-                    s_o[r][0] = SD.rp.o[0];
-                    s_o[r][1] = SD.rp.o[1];
-                    s_o[r][2] = SD.rp.o[2];
-                    s_tau[r] = SD.rp.tau;
-                }
+                const ScanDev &SD = B.scans[s_scan[s_list[j0 + r]]];
+                s_o[r][0] = SD.rp.o[0];
+                s_o[r][1] = SD.rp.o[1];
+                s_o[r][2] = SD.rp.o[2];
+                s_tau[r] = SD.rp.tau;
             }
             __syncthreads();
             for (uint32_t e = threadIdx.x; e < gsum; e += kTileBlock) {
                 // which run of the group entry e belongs to
                 int r = 0;
                 uint32_t ee = e;
-                while (ee >= s_cnt[sq0 + r]) {
-                    ee -= s_cnt[sq0 + r];
+                while (ee >= s_cnt[s_list[j0 + r]]) {
+                    ee -= s_cnt[s_list[j0 + r]];
                     ++r;
                 }
-                const uint32_t beg = s_beg[sq0 + r];
+                const uint32_t beg = s_beg[s_list[j0 + r]];
                 // the run lies inside the entry buffer unless the fill overflowed
                 if (beg + ee >= H.cap) continue;
                 const uint4 ra = B.entries[beg + ee];
@@ -550,8 +556,7 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                         if (upd[r]) atomicAdd(&s_upd[r], upd[r]);
             } else {
                 // a single busy slot: merge straight into HBM, runs of 8
-                int rb = 0;
-                while (s_cnt[sq0 + rb] == 0u) ++rb;
+                const int rb = 0;
                 uint32_t updated = 0;
                 for (uint32_t v0 = threadIdx.x * 8u; v0 < tvox; v0 += kTileBlock * 8u) {
                     const int32_t rz0 = (int32_t)(v0 & (ez - 1)) + t0[2];
@@ -567,8 +572,8 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                 if (H.want_stats && updated) atomicAdd(&s_upd[rb], updated);
             }
             __syncthreads();
-            if (threadIdx.x < (uint32_t)ng && s_cnt[sq0 + threadIdx.x]) {
-                const uint32_t k = (uint32_t)(sq0 + threadIdx.x) * H.gtiles + g;
+            if (threadIdx.x < (uint32_t)ng) {
+                const uint32_t k = (uint32_t)s_list[j0 + threadIdx.x] * H.gtiles + g;
                 B.counts[k] = 0;  // ready for the next batch
                 if (H.want_stats) {
                     B.tile_vis[k] = s_vis[threadIdx.x];
