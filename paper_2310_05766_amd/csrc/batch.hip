@@ -86,6 +86,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
         // the allocation counters of the previous batch are done with (the
         // grid always has a block 0, also for a batch without points)
         B.ctl->n_nonempty = 0;
+        B.ctl->n_light = 0;
         B.ctl->entries = 0;
         B.ctl->overflow = 0;
         for (int q = 0; q < kQueues; ++q) B.ctl->work[q] = 0;
@@ -218,11 +219,14 @@ __device__ __forceinline__ int32_t map_of_tile(const BatchArrays &B, int32_t nma
 // keeps them few). Four lanes share a tile, each summing a quarter of its
 // sequence slots, so that the chains of count loads stay short.
 constexpr int kAllocTiles = kAllocBlock / 4;
+// A tile with this many entries or more is listed first: the persistent tile
+// pass then starts the longest tiles early instead of ending on one of them.
+constexpr uint32_t kHeavyTile = 2048;
 
 __global__ __launch_bounds__(kAllocBlock) void k_alloc(BatchArrays B)
 {
-    __shared__ uint32_t s_wc[kAllocBlock / 64], s_wn[kAllocBlock / 64];
-    __shared__ uint32_t s_base_c, s_base_n;
+    __shared__ uint32_t s_wc[kAllocBlock / 64], s_wn[kAllocBlock / 64], s_wl[kAllocBlock / 64];
+    __shared__ uint32_t s_base_c, s_base_n, s_base_l;
     const BatchHdr H = *B.hdr;
     if (blockIdx.x * kAllocTiles >= H.gtiles) return;
     const uint32_t t = blockIdx.x * kAllocTiles + threadIdx.x / 4;
@@ -242,34 +246,43 @@ __global__ __launch_bounds__(kAllocBlock) void k_alloc(BatchArrays B)
     }
     const uint32_t tile_c = (uint32_t)__shfl((int)pq, (int)(lane() | 3u));
     // inclusive prefix over the wave's tiles (counted on each tile's last lane)
-    uint32_t pc = part == 3u ? tile_c : 0u, pn = (part == 3u && tile_c) ? 1u : 0u;
+    const bool heavy = tile_c >= kHeavyTile;
+    uint32_t pc = part == 3u ? tile_c : 0u, pn = (part == 3u && heavy) ? 1u : 0u;
+    uint32_t pl = (part == 3u && tile_c && !heavy) ? 1u : 0u;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
         const uint32_t a = (uint32_t)__shfl_up((int)pc, off);
         const uint32_t b = (uint32_t)__shfl_up((int)pn, off);
+        const uint32_t d = (uint32_t)__shfl_up((int)pl, off);
         if (lane() >= (uint32_t)off) {
             pc += a;
             pn += b;
+            pl += d;
         }
     }
     pc = (uint32_t)__shfl((int)pc, (int)(lane() | 3u));
     pn = (uint32_t)__shfl((int)pn, (int)(lane() | 3u));
+    pl = (uint32_t)__shfl((int)pl, (int)(lane() | 3u));
     if (lane() == 63) {
         s_wc[wave] = pc;
         s_wn[wave] = pn;
+        s_wl[wave] = pl;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t sc = 0, sn = 0;
+        uint32_t sc = 0, sn = 0, sl = 0;
         for (int k = 0; k < kAllocBlock / 64; ++k) {
-            const uint32_t a = s_wc[k], b = s_wn[k];
+            const uint32_t a = s_wc[k], b = s_wn[k], d = s_wl[k];
             s_wc[k] = sc;
             s_wn[k] = sn;
+            s_wl[k] = sl;
             sc += a;
             sn += b;
+            sl += d;
         }
         s_base_c = sc ? atomicAdd(&B.ctl->entries, sc) : 0u;
         s_base_n = sn ? atomicAdd(&B.ctl->n_nonempty, sn) : 0u;
+        s_base_l = sl ? atomicAdd(&B.ctl->n_light, sl) : 0u;
     }
     __syncthreads();
     if (tile_c) {
@@ -285,7 +298,8 @@ __global__ __launch_bounds__(kAllocBlock) void k_alloc(BatchArrays B)
             off += ck;
         }
         if (part == 0u) {
-            const uint32_t slot = s_base_n + s_wn[wave] + pn - 1u;
+            const uint32_t slot =
+                heavy ? s_base_n + s_wn[wave] + pn - 1u : H.gtiles - 1u - (s_base_l + s_wl[wave] + pl - 1u);
             B.nonempty[slot] = t;
             B.nonempty_map[slot] = (uint32_t)map_of_tile(B, H.nmaps, t);
         }
@@ -412,7 +426,8 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
     const int32_t G = H.G;
     int16_t *c_sdf = reinterpret_cast<int16_t *>(s_keys + (size_t)G * tvox);
     int16_t *c_w = c_sdf + tvox;
-    const uint32_t nne = B.ctl->n_nonempty;
+    // heavy tiles first (from the list's start), then the others (from its end)
+    const uint32_t nheavy = B.ctl->n_nonempty, nne = nheavy + B.ctl->n_light;
     const uint32_t ez = 1u << H.lt[2], ey = 1u << H.lt[1];
     const int32_t sh[3] = {H.lt[1] + H.lt[2], H.lt[2], 0};  // LDS index shift per axis
     uint32_t job = blockIdx.x;
@@ -420,8 +435,9 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
     const uint32_t queue = blockIdx.x % kQueues;
     for (uint32_t v = threadIdx.x; v < (uint32_t)G * tvox; v += kTileBlock) s_keys[v] = kEmptyKey;
     while (job < nne) {
-        const uint32_t g = uniform(B.nonempty[job]);
-        const int32_t mb = uniform((int32_t)B.nonempty_map[job]);
+        const uint32_t at = job < nheavy ? job : H.gtiles - 1u - (job - nheavy);
+        const uint32_t g = uniform(B.nonempty[at]);
+        const int32_t mb = uniform((int32_t)B.nonempty_map[at]);
         // the tile's runs, one load per sequence slot, all in flight
         // together; the first wave (at most 64 slots) lists the busy slots in
         // order, so that groups of G hold busy slots only

@@ -64,7 +64,9 @@ struct BatchHdr {
 constexpr int kQueues = 8;  // tile job queues, one per XCD (workgroup b runs on XCD b % 8)
 
 struct BatchCtl {
-    uint32_t n_nonempty, entries, overflow, pad;
+    uint32_t n_nonempty;  // busy tiles with heavy work, listed from the list's start
+    uint32_t entries, overflow;
+    uint32_t n_light;     // the other busy tiles, listed from the list's end
     uint32_t work[kQueues];  // next job of each queue
 };
 
