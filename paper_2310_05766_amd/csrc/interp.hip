@@ -38,6 +38,7 @@ namespace tsdf {
 namespace {
 
 constexpr int kInterpBlock = 256;
+constexpr int kCarveChunkLog2 = 6;
 
 // rdiv(n, d) = sign(n) floor((2|n| + d) / 2d), to nearest with ties away
 // from zero, for a divisor 0 < d < 2^32 fixed per ray (given as 2d and
@@ -190,9 +191,23 @@ __device__ __forceinline__ void offer_key(const InterpScan &P, int64_t sl, uint6
 // candidate to it (that neighbour offers it, or is covered the same way by
 // a smaller key further left). A lane whose walk has ended still shows the
 // last candidate it held, which was offered.
-__global__ __launch_bounds__(kInterpBlock) void k_carve_scan(InterpScan P)
+// Free-space walks differ a lot in length (a wave runs as long as its longest
+// lane), so each ray's free segment is cut into chunks: chunk c walks only
+// the slab of voxels [(k0 + c) C, (k0 + c + 1) C) along the segment's longest
+// axis, slabs of C = 2^kCarveChunkLog2 voxels in global coordinates counted
+// from the slab k0 that holds the segment's lowest voxel inside the window.
+// A wave holds one chunk of 64 consecutive rays, and consecutive waves take
+// the chunks of one group of rays in turn (wave w: rays 64 (w / nch) + lane,
+// chunk w mod nch), which spreads the atomics near the sensor, where all rays
+// meet, over the whole launch instead of its first waves. Chunk 0 also walks
+// the band.
+__global__ __launch_bounds__(kInterpBlock) void k_carve_scan(InterpScan P, int64_t npad)
 {
-    const int64_t i = (int64_t)blockIdx.x * kInterpBlock + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * kInterpBlock + threadIdx.x;
+    const int64_t nch = (int64_t)gridDim.x * kInterpBlock / npad;
+    const int64_t w = t >> 6;
+    const int64_t i = (w / nch) * 64 + (t & 63);
+    const int32_t chunk = (int32_t)(w % nch);
     const int lane = (int)(threadIdx.x & 63u);
     uint64_t valid = 0, visits = 0;
     int32_t q[3];
@@ -205,7 +220,35 @@ __global__ __launch_bounds__(kInterpBlock) void k_carve_scan(InterpScan P)
     const bool ray = i < P.n && quantise(P.xyz[3 * i], P.xyz[3 * i + 1], P.xyz[3 * i + 2], P.rp, q) &&
                      make_ray(q, P.rp, R);
     FreeWalk F;
-    bool act = ray && R.r > (double)P.rp.tau && free_walk_init(R, P.rp, lo, hi, F);
+    bool act = false;
+    if (ray && R.r > (double)P.rp.tau) {
+        // the free segment [o, S]: its longest axis and its voxel range there
+        int da = 0;
+        int64_t best = -1;
+        for (int a = 0; a < 3; ++a) {
+            const int64_t L = (int64_t)R.S[a] - P.rp.o[a];
+            const int64_t m = L < 0 ? -L : L;
+            if (m > best) {
+                best = m;
+                da = a;
+            }
+        }
+        const int32_t g0 = P.rp.o[da] >> 10, g1 = R.S[da] >> 10;
+        int32_t gmin = g0 < g1 ? g0 : g1, gmax = g0 < g1 ? g1 : g0;
+        gmin = gmin > lo[da] ? gmin : lo[da];
+        gmax = gmax < hi[da] - 1 ? gmax : hi[da] - 1;
+        const int32_t k = (gmin >> kCarveChunkLog2) + chunk;
+        const int32_t slo = k << kCarveChunkLog2, shi = slo + (1 << kCarveChunkLog2);
+        if (gmin <= gmax && slo <= gmax) {
+            lo[da] = lo[da] > slo ? lo[da] : slo;
+            hi[da] = hi[da] < shi ? hi[da] : shi;
+            act = lo[da] < hi[da] && free_walk_init(R, P.rp, lo, hi, F);
+        }
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = P.origin[a];
+            hi[a] = P.origin[a] + P.dims[a];
+        }
+    }
     int64_t sl = -1;
     uint64_t key = 0;
     while (__any(act)) {
@@ -221,7 +264,7 @@ __global__ __launch_bounds__(kInterpBlock) void k_carve_scan(InterpScan P)
             act = free_walk_next(F);
         }
     }
-    if (ray) {
+    if (ray && chunk == 0) {
         valid = 1;
         Walk W;
         walk_init(R, W);
@@ -285,9 +328,16 @@ hipError_t launch_interp(const InterpScan &P, int64_t nvox, hipStream_t stream)
 {
     if (P.n > 0) {
         const int64_t blocks = (P.n + kInterpBlock - 1) / kInterpBlock;
-        if (P.carve)
-            hipLaunchKernelGGL(k_carve_scan, dim3((uint32_t)blocks), dim3(kInterpBlock), 0, stream, P);
-        else
+        if (P.carve) {
+            // chunks of a ray: as many slabs as the window's longest side
+            // spans, plus one for a slab boundary inside it
+            int32_t dmax = P.dims[0] > P.dims[1] ? P.dims[0] : P.dims[1];
+            dmax = dmax > P.dims[2] ? dmax : P.dims[2];
+            const int64_t nchunk = ((int64_t)dmax + (1 << kCarveChunkLog2) - 1) / (1 << kCarveChunkLog2) + 1;
+            const int64_t npad = blocks * kInterpBlock;
+            hipLaunchKernelGGL(k_carve_scan, dim3((uint32_t)(blocks * nchunk)), dim3(kInterpBlock), 0, stream, P,
+                               npad);
+        } else
             hipLaunchKernelGGL(k_interp_scan, dim3((uint32_t)blocks), dim3(kInterpBlock), 0, stream, P);
     }
     // four waves per block, one group of 64 runs per wave
