@@ -417,6 +417,7 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
     __shared__ uint32_t s_beg[kMaxSeq], s_cnt[kMaxSeq];
     __shared__ int32_t s_scan[kMaxSeq];
     __shared__ int32_t s_o[kMaxGroup][3], s_tau[kMaxGroup];
+    __shared__ uint32_t s_gbeg[kMaxGroup];  // the group's runs: first entry
     __shared__ uint32_t s_vis[kMaxGroup], s_upd[kMaxGroup];
     __shared__ uint32_t s_busy, s_job;
     __shared__ uint8_t s_list[kMaxSeq];  // the tile's busy sequence slots, in order
@@ -485,13 +486,21 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
         for (int j0 = 0; j0 < nbusy; j0 += G) {
             // a group: busy slots j0 .. j0 + ng - 1 of the list, in order
             const int ng = min(G, nbusy - j0);
+            // inclusive prefix of the group's run lengths (uniform: scalar
+            // registers), so that an entry finds its run by comparisons
+            uint32_t pre[kMaxGroup];
             uint32_t gsum = 0;
-            for (int r = 0; r < ng; ++r) gsum += s_cnt[s_list[j0 + r]];
+#pragma unroll
+            for (int r = 0; r < kMaxGroup; ++r) {
+                if (r < ng) gsum += s_cnt[s_list[j0 + r]];
+                pre[r] = uniform(gsum);
+            }
             gsum = uniform(gsum);
             if (threadIdx.x < (uint32_t)ng) {
                 const int r = (int)threadIdx.x;
                 s_vis[r] = 0;
                 s_upd[r] = 0;
+                s_gbeg[r] = s_beg[s_list[j0 + r]];
                 const ScanDev &SD = B.scans[s_scan[s_list[j0 + r]]];
                 s_o[r][0] = SD.rp.o[0];
                 s_o[r][1] = SD.rp.o[1];
@@ -500,14 +509,18 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
             }
             __syncthreads();
             for (uint32_t e = threadIdx.x; e < gsum; e += kTileBlock) {
-                // which run of the group entry e belongs to
+                // which run of the group entry e belongs to (the group's
+                // runs are all non-empty: pre rises strictly up to gsum)
                 int r = 0;
-                uint32_t ee = e;
-                while (ee >= s_cnt[s_list[j0 + r]]) {
-                    ee -= s_cnt[s_list[j0 + r]];
-                    ++r;
+                uint32_t base = 0;
+#pragma unroll
+                for (int k = 0; k < kMaxGroup - 1; ++k) {
+                    const bool past = e >= pre[k];
+                    r += past ? 1 : 0;
+                    base = past ? pre[k] : base;
                 }
-                const uint32_t beg = s_beg[s_list[j0 + r]];
+                const uint32_t ee = e - base;
+                const uint32_t beg = s_gbeg[r];
                 // the run lies inside the entry buffer unless the fill overflowed
                 if (beg + ee >= H.cap) continue;
                 const uint4 ra = B.entries[beg + ee];
