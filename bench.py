@@ -267,7 +267,7 @@ def carve_leg(torch, synth, TsdfMap, n_scans: int = 50, reps: int = 3):
             "hbm_frac": B * reps / gpu_s / 1e9 / HBM_PEAK_GBS,
             "atomic_roofline": {"bound": ATOMIC_BOUND, "atomics_per_s": probe, "visits_per_s": vps,
                                 "frac": vps / probe["window_key_volume"],
-                                "note": "a visit issues at most one atomic; the lockstep check leaves fewer"}}
+                                "note": "a visit issues at most one atomic; the lockstep check and the read before the atomic leave fewer, so frac can exceed 1"}}
 
 
 def uneven_batch_leg(torch, synth, reps: int = 3):
