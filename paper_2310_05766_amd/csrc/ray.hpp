@@ -63,6 +63,17 @@ __device__ __forceinline__ uint64_t isqrt_u64(uint64_t n)
 // afterwards, so its accuracy only decides how many correction steps run.
 __device__ __forceinline__ double approx_rcp(double d) { return __builtin_amdgcn_rcp(d); }
 
+// min(a, b) of two doubles that are never NaN, as one v_min_f64. fmin must
+// first quiet signalling NaNs, one v_max_f64 x, x per operand the compiler
+// cannot trace to an arithmetic result (loop-carried times, invariants), and
+// the walk loops would pay for that on every step.
+__device__ __forceinline__ double min_nonan(double a, double b)
+{
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // min(floor(a / d), cap) for exact integers 0 <= a < 2^53, 0 < d < 2^34,
 // cap <= 2^17, from an estimate a * inv_d (inv_d ~ 1/d, relative error far
 // below 2^-17): capped at cap (callers clamp the quotient there anyway), the
@@ -147,10 +158,10 @@ __device__ __forceinline__ int32_t voxel_sdf(double n, const Ray &R, int32_t tau
 {
     const double a = 2.0 * fabs(n) + R.r;
     const double cap = (double)tau + 1.0;
-    double k = fmin(floor(a * R.inv_r2), cap);
+    double k = min_nonan(floor(a * R.inv_r2), cap);
     k -= k * R.r2 > a ? 1.0 : 0.0;
     k += (k < cap && __fma_rn(k, R.r2, R.r2) <= a) ? 1.0 : 0.0;
-    const int32_t s = (int32_t)fmin(k, (double)tau);
+    const int32_t s = (int32_t)min_nonan(k, (double)tau);
     return n < 0 ? -s : s;
 }
 
@@ -224,7 +235,7 @@ __device__ __forceinline__ void walk_init(const Ray &R, Walk &W)
 // Advance to the next cell; false when the segment ends.
 __device__ __forceinline__ bool walk_next(Walk &W)
 {
-    const double tm = fmin(W.T[0], fmin(W.T[1], W.T[2]));
+    const double tm = min_nonan(W.T[0], min_nonan(W.T[1], W.T[2]));
     const bool e0 = W.T[0] == tm, e1 = W.T[1] == tm, e2 = W.T[2] == tm;
     const bool any_up = (e0 && W.step[0] > 0) || (e1 && W.step[1] > 0) || (e2 && W.step[2] > 0);
     const int dir = any_up ? 1 : -1;
@@ -239,7 +250,7 @@ __device__ __forceinline__ bool walk_next(Walk &W)
 // (0: increasing crossings, 1: decreasing ones).
 __device__ __forceinline__ bool walk_next_event(Walk &W, double &t_ev, int &typ)
 {
-    const double tm = fmin(W.T[0], fmin(W.T[1], W.T[2]));
+    const double tm = min_nonan(W.T[0], min_nonan(W.T[1], W.T[2]));
     const bool e0 = W.T[0] == tm, e1 = W.T[1] == tm, e2 = W.T[2] == tm;
     const bool any_up = (e0 && W.step[0] > 0) || (e1 && W.step[1] > 0) || (e2 && W.step[2] > 0);
     const int dir = any_up ? 1 : -1;
@@ -381,13 +392,16 @@ __device__ __forceinline__ void box_walk_from(const Walk &W, const int32_t lo[3]
 // or the segment ends.
 __device__ __forceinline__ bool box_walk_next(BoxWalk &V)
 {
-    const double tm = fmin(V.T[0], fmin(V.T[1], V.T[2]));
+    const double tm = min_nonan(V.T[0], min_nonan(V.T[1], V.T[2]));
     if (tm > V.lim) return false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
+        // x + (0 or 1) dx as one fma: exact (the sums are integers below
+        // 2^53, and an axis that never crosses has dT = dn = 0)
         const bool e = V.T[a] == tm;
-        V.T[a] += e ? V.dT[a] : 0.0;
-        V.n += e ? V.dn[a] : 0.0;
+        const double ef = e ? 1.0 : 0.0;
+        V.T[a] = __fma_rn(ef, V.dT[a], V.T[a]);
+        V.n = __fma_rn(ef, V.dn[a], V.n);
         V.lv += e ? V.dlv[a] : 0;
     }
     return true;
