@@ -58,7 +58,7 @@ __device__ __forceinline__ void ray_of_entry(const uint4 &ra, const uint4 &rb, c
     R.q[2] = (int32_t)ra.w;
     R.r = (double)rb.x;
     R.r2 = 2.0 * R.r;
-    R.inv_r2 = approx_rcp(R.r2);
+    R.inv_r2 = refined_rcp(R.r2);  // band_key's precondition
     const bool near = R.r <= (double)tau;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -542,10 +542,11 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                 BoxWalk V;
                 box_walk_from(W, blo, bhi, sh, V);
                 uint64_t *kb = s_keys + (size_t)r * tvox;
+                const double taud = (double)tau;
+                const uint32_t ihi = i >> 16, ilo = i << 16;
                 uint32_t visits = 0;
                 do {
-                    const int32_t sd = voxel_sdf(V.n, R, tau);
-                    atomicMin((unsigned long long *)&kb[V.lv], (unsigned long long)pack_key(sd, i));
+                    atomicMin((unsigned long long *)&kb[V.lv], (unsigned long long)band_key(V.n, R, taud, ihi, ilo));
                     ++visits;
                 } while (box_walk_next(V));
                 if (H.want_stats && visits) atomicAdd(&s_vis[r], visits);

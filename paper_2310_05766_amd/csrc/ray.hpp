@@ -173,6 +173,36 @@ __device__ __forceinline__ uint64_t pack_key(int32_t s, uint32_t i)
     return ((uint64_t)as << 48) | ((uint64_t)i << 16) | (uint64_t)(uint16_t)(int16_t)s;
 }
 
+// 1 / d to within a few units of 2^-53: the hardware estimate (relative
+// error far below 2^-20) and two Newton steps, each of which squares the
+// error and adds one rounding.
+__device__ __forceinline__ double refined_rcp(double d)
+{
+    double y = approx_rcp(d);
+    double e = __fma_rn(-d, y, 1.0);
+    y = __fma_rn(y, e, y);
+    e = __fma_rn(-d, y, 1.0);
+    return __fma_rn(y, e, y);
+}
+
+// pack_key(voxel_sdf(n, R, tau), i) for a voxel of the band walk, with
+// R.inv_r2 = refined_rcp(2r), taud = tau, ihi = i >> 16 and ilo = i << 16.
+// Such a voxel lies within one voxel diagonal of [S, E], so |q - c| <=
+// tau (1 + 1/r) + 888 (S = o when r <= tau) and x = (2|n| + r) / 2r <
+// 2^17.1. The estimate a * inv_r2 is then off by under 2^-34.8, while a
+// non-integer x lies at least 1 / 2r > 2^-32.8 from the next integer: its
+// floor is floor(x), or x - 1 when x is an integer, and one upward
+// correction makes it exact. No cap is needed: x is far below 2^53 / 2r.
+__device__ __forceinline__ uint64_t band_key(double n, const Ray &R, double taud, uint32_t ihi, uint32_t ilo)
+{
+    const double a = 2.0 * fabs(n) + R.r;
+    double k = floor(a * R.inv_r2);
+    k += __fma_rn(k, R.r2, R.r2) <= a ? 1.0 : 0.0;  // (k + 1) 2r <= a
+    const uint32_t as = (uint32_t)min_nonan(k, taud);
+    const uint32_t lo = ilo | (n < 0 ? (0x10000u - as) & 0xffffu : as);
+    return (uint64_t)(as << 16 | ihi) << 32 | lo;
+}
+
 // Exact walk over the cells { floor((P(t) - base) / cell) : t in [0, 1] },
 // P(t) = S + t (E - S), with cell = 2^lc per axis in fixed point (lc = 10:
 // voxels; 10 + log2(tile edge): tiles). Axis crossings are ordered by their
