@@ -1,0 +1,85 @@
+// Host build of the device ray arithmetic (csrc/ray.hpp) checked against
+// exact integer rounding: for the voxels of band walks of random rays, the
+// tile pass's band_key (Newton-refined reciprocal, one upward correction, no
+// cap) and pack_key(voxel_sdf(...)) must both equal
+//   pack_key(sign(n) min(floor((2|n| + r) / 2r), tau), i),  n = (q - c) . D,
+// computed in 128-bit integers. Rays with tiny components make r small, so
+// exact ties (2|n| + r divisible by 2r) are frequent. The hardware
+// reciprocal estimate is replaced by 1/d scaled by (1 + p); p runs over
+// errors up to 2^-14 for band_key, whose Newton steps absorb them, and up to
+// 2^-20 for voxel_sdf. The test driver defines RAY_HPP (a copy of ray.hpp
+// whose one inline-asm minimum is replaced by a compare).
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#define __device__
+#define __forceinline__ inline
+#define __fma_rn(a, b, c) std::fma((a), (b), (c))
+#define __dmul_rn(a, b) ((a) * (b))
+static double g_pert = 0.0;
+#define __builtin_amdgcn_rcp(x) ((1.0 / (x)) * (1.0 + g_pert))
+using std::fabs;
+using std::floor;
+using std::fmin;
+using std::isfinite;
+using std::rint;
+using std::sqrt;
+#include RAY_HPP
+using namespace tsdf;
+
+int main(int argc, char **argv)
+{
+    std::mt19937_64 rng(argc > 1 ? strtoull(argv[1], nullptr, 10) : 7);
+    const int iters = argc > 2 ? atoi(argv[2]) : 20000;
+    const double perts[] = {0.0, 0x1p-20, -0x1p-20, 0x1p-14, -0x1p-14, 0x1p-30, -0x1p-45};
+    long bad = 0, vox = 0, ties = 0, rays = 0;
+    for (int it = 0; it < iters; ++it) {
+        g_pert = perts[it % 7];
+        RayParams P{};
+        const int64_t lim = 1ll << std::uniform_int_distribution<int>(0, 31)(rng);
+        int32_t q[3];
+        for (int a = 0; a < 3; ++a) {
+            const int64_t o = std::uniform_int_distribution<int64_t>(-(1ll << 29), 1ll << 29)(rng);
+            int64_t d = std::uniform_int_distribution<int64_t>(-lim, lim)(rng);
+            if (it % 5 == 0 && a > 0) d = std::uniform_int_distribution<int64_t>(-2, 2)(rng);
+            const int64_t p = o + d;  // the fixed point keeps |q| < 2^30
+            P.o[a] = (int32_t)o;
+            q[a] = (int32_t)(p > -(1ll << 30) && p < (1ll << 30) ? p : o);
+        }
+        P.tau = it % 3 == 0 ? 32767 : std::uniform_int_distribution<int>(1, 32767)(rng);
+        Ray R;
+        if (!make_ray(q, P, R)) continue;
+        ++rays;
+        Ray Rk = R;
+        Rk.inv_r2 = refined_rcp(Rk.r2);
+        const uint32_t i = (uint32_t)rng();
+        Walk W;
+        walk_init(R, W);
+        do {
+            __int128 n = 0;
+            for (int a = 0; a < 3; ++a)
+                n += (__int128)((int64_t)q[a] - (1024 * (int64_t)W.g[a] + 512)) * ((int64_t)q[a] - P.o[a]);
+            const __int128 an = n < 0 ? -n : n;
+            const __int128 r = (__int128)(uint64_t)R.r;
+            const __int128 num = 2 * an + r, den = 2 * r;
+            const __int128 k = num / den;
+            ties += num % den == 0;
+            int32_t s = (int32_t)(k < P.tau ? k : P.tau);
+            if (n < 0) s = -s;
+            const uint64_t want = pack_key(s, i);
+            const bool ok_band = (double)n == W.n && band_key(W.n, Rk, (double)P.tau, i >> 16, i << 16) == want;
+            const bool ok_sdf = fabs(g_pert) > 0x1p-18 || pack_key(voxel_sdf(W.n, R, P.tau), i) == want;
+            if (!ok_band || !ok_sdf) {
+                if (bad < 5)
+                    printf("mismatch: r=%llu tau=%d n=%.17g perturbation %g\n", (unsigned long long)(uint64_t)R.r,
+                           P.tau, (double)n, g_pert);
+                ++bad;
+            }
+            ++vox;
+        } while (walk_next(W));
+    }
+    printf("rays %ld voxels %ld ties %ld mismatches %ld\n", rays, vox, ties, bad);
+    return bad != 0 || ties == 0;
+}
