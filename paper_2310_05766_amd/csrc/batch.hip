@@ -374,6 +374,15 @@ __device__ __forceinline__ int64_t slot_of_rel(const MapDev &MD, int32_t rx, int
 // (the compiler cannot tell that values read from LDS or memory are uniform,
 // and keeps them, and all derived from them, in vector registers otherwise).
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+// LDS byte address of a shared-memory pointer, and back: an address kept
+// in one integer register needs no base added per access.
+typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+__device__ __forceinline__ uint32_t lds_address(uint64_t *p) { return (uint32_t)(uintptr_t)(lds_u64 *)p; }
+__device__ __forceinline__ unsigned long long *lds_pointer(int32_t a)
+{
+    return (unsigned long long *)(lds_u64 *)(uintptr_t)(uint32_t)a;
+}
 __device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 template <typename T>
 __device__ __forceinline__ T *uniform(T *p)
@@ -431,6 +440,7 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
     const uint32_t nheavy = B.ctl->n_nonempty, nne = nheavy + B.ctl->n_light;
     const uint32_t ez = 1u << H.lt[2], ey = 1u << H.lt[1];
     const int32_t sh[3] = {H.lt[1] + H.lt[2], H.lt[2], 0};  // LDS index shift per axis
+    const int32_t shb[3] = {sh[0] + 3, sh[1] + 3, 3};          // the same, in bytes of 8-byte keys
     uint32_t job = blockIdx.x;
     if (job >= nne) return;
     const uint32_t queue = blockIdx.x % kQueues;
@@ -539,14 +549,14 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                 walk_advance(W, c);
                 if (!walk_enter_box(W, blo, bhi)) continue;
                 // the voxels of the walk inside the box are one run
+                // (the walk carries the key's LDS address itself)
                 BoxWalk V;
-                box_walk_from(W, blo, bhi, sh, V);
-                uint64_t *kb = s_keys + (size_t)r * tvox;
+                box_walk_from(W, blo, bhi, shb, lds_address(s_keys + (size_t)r * tvox), V);
                 const double taud = (double)tau;
                 const uint32_t ihi = i >> 16, ilo = i << 16;
                 uint32_t visits = 0;
                 do {
-                    atomicMin((unsigned long long *)&kb[V.lv], (unsigned long long)band_key(V.n, R, taud, ihi, ilo));
+                    atomicMin(lds_pointer(V.lv), (unsigned long long)band_key(V.n, R, taud, ihi, ilo));
                     ++visits;
                 } while (box_walk_next(V));
                 if (H.want_stats && visits) atomicAdd(&s_vis[r], visits);

@@ -200,8 +200,9 @@ __device__ __forceinline__ void offer_key(const InterpScan &P, int64_t sl, uint6
 // the chunks of one group of rays in turn (wave w: rays 64 (w / nch) + lane,
 // chunk w mod nch), which spreads the atomics near the sensor, where all rays
 // meet, over the whole launch instead of its first waves. Chunk 0 also walks
-// the band.
-__global__ __launch_bounds__(kInterpBlock) void k_carve_scan(InterpScan P, int64_t npad)
+// the band. Four waves per SIMD: held to five, the walk state spills.
+__global__ __launch_bounds__(kInterpBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_carve_scan(InterpScan P,
+                                                                                                      int64_t npad)
 {
     const int64_t t = (int64_t)blockIdx.x * kInterpBlock + threadIdx.x;
     const int64_t nch = (int64_t)gridDim.x * kInterpBlock / npad;

@@ -195,7 +195,7 @@ __device__ __forceinline__ double refined_rcp(double d)
 // correction makes it exact. No cap is needed: x is far below 2^53 / 2r.
 __device__ __forceinline__ uint64_t band_key(double n, const Ray &R, double taud, uint32_t ihi, uint32_t ilo)
 {
-    const double a = 2.0 * fabs(n) + R.r;
+    const double a = __fma_rn(2.0, fabs(n), R.r);  // exact: below 2^50
     double k = floor(a * R.inv_r2);
     k += __fma_rn(k, R.r2, R.r2) <= a ? 1.0 : 0.0;  // (k + 1) 2r <= a
     const uint32_t as = (uint32_t)min_nonan(k, taud);
@@ -241,13 +241,10 @@ __device__ __forceinline__ void walk_init_cells(const Ray &R, Walk &W, const int
     for (int a = 0; a < 3; ++a) {
         const double cell = (double)(1 << lc[a]);
         const double lo = (double)base[a] + cell * (double)W.g[a];
-        if (W.step[a] > 0) {
-            W.T[a] = (lo + cell - (double)R.S[a]) * other[a];
-        } else if (W.step[a] < 0) {
-            W.T[a] = ((double)R.S[a] - lo) * other[a];
-        } else {
-            W.T[a] = INFINITY;
-        }
+        // distance from S to the cell's face ahead (selects, no branches)
+        const double x = (double)R.S[a] - lo;
+        const double ahead = W.step[a] > 0 ? cell - x : x;
+        W.T[a] = W.step[a] != 0 ? ahead * other[a] : INFINITY;
         W.dT[a] = cell * other[a];
         n += ((double)R.q[a] - (lo + 512.0)) * R.D[a];
         W.dn[a] = -1024.0 * R.D[a];
@@ -378,8 +375,8 @@ __device__ __forceinline__ bool walk_enter_box(Walk &W, const int32_t lo[3], con
 // taken for T <= lam, decreasing for T < lam" becomes T' <= 2 lam for both
 // (T integer). Leaving the box is one more event per axis, so the whole
 // stopping rule is one bound: T' <= lim, lim = min(2 lam, first exit - 1).
-// The walk carries the voxel's index in the box (LDS layout, z fastest)
-// instead of its coordinates. Magnitudes: T' < 2^53 (T < 2^52, and a box
+// The walk carries the LDS byte address of the voxel's key (a buffer in z
+// fastest layout) instead of its coordinates. Magnitudes: T' < 2^53 (T < 2^52, and a box
 // exit lies at most 64 crossings past the current time).
 struct BoxWalk {
     double T[3], dT[3];
@@ -389,12 +386,12 @@ struct BoxWalk {
 };
 
 // From a voxel walk that walk_enter_box has placed inside [lo, hi); sh[a] is
-// the LDS index shift of axis a.
+// the byte shift of axis a in a key buffer at LDS address base.
 __device__ __forceinline__ void box_walk_from(const Walk &W, const int32_t lo[3], const int32_t hi[3],
-                                              const int32_t sh[3], BoxWalk &V)
+                                              const int32_t sh[3], uint32_t base, BoxWalk &V)
 {
     double first_exit = INFINITY;
-    V.lv = 0;
+    V.lv = (int32_t)base;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         V.lv += (W.g[a] - lo[a]) << sh[a];
