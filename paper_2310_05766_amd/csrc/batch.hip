@@ -122,14 +122,18 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
     }
     const uint32_t valid = active ? 1u : 0u;
     const uint32_t key0 = (uint32_t)SD.seq * H.gtiles + MD.tile_base;
+    // the map's tile counts in registers: loads through MD inside the walk
+    // would be repeated after every atomic (they may alias)
+    const uint32_t nt0 = (uint32_t)__builtin_amdgcn_readfirstlane(MD.nt[0]);
+    const uint32_t nt1 = (uint32_t)__builtin_amdgcn_readfirstlane(MD.nt[1]);
+    const uint32_t nt2 = (uint32_t)__builtin_amdgcn_readfirstlane(MD.nt[2]);
     int ne = 0;
     double t_in = -1.0;  // event that entered the current tile (none for the first)
     int typ_in = 0;
     while (active) {
-        if ((uint32_t)W.g[0] < (uint32_t)MD.nt[0] && (uint32_t)W.g[1] < (uint32_t)MD.nt[1] &&
-            (uint32_t)W.g[2] < (uint32_t)MD.nt[2]) {
+        if ((uint32_t)W.g[0] < nt0 && (uint32_t)W.g[1] < nt1 && (uint32_t)W.g[2] < nt2) {
             const uint32_t key =
-                key0 + ((uint32_t)W.g[0] * (uint32_t)MD.nt[1] + (uint32_t)W.g[1]) * (uint32_t)MD.nt[2] + (uint32_t)W.g[2];
+                key0 + ((uint32_t)W.g[0] * nt1 + (uint32_t)W.g[1]) * nt2 + (uint32_t)W.g[2];
             uint32_t h = hash_slot(key), slot = 0xffffu;
             for (int probe = 0; probe < kHashSlots; ++probe) {
                 const uint32_t old = atomicCAS(&h_key[h], 0u, key + 1u);
