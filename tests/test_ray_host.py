@@ -1,8 +1,10 @@
-"""Host build of the device ray arithmetic against exact integer rounding
-(tests/host/band_key_check.cpp): the band keys of the tile pass and the
-signed distance of the other walks, over band walks of random rays with
-frequent exact ties, at perturbed reciprocal estimates. CPU only: g++
-compiles csrc/ray.hpp with its one inline-asm minimum replaced."""
+"""Host builds of the device ray arithmetic (tests/host/*.cpp). CPU only:
+g++ compiles csrc/ray.hpp with its one inline-asm minimum replaced.
+* band_key_check: the band keys of the tile pass and the signed distance of
+  the other walks against exact integer rounding, over band walks of random
+  rays with frequent exact ties, at perturbed reciprocal estimates;
+* box_walk_check: the tile pass's resumed box walks against the plain voxel
+  walk."""
 import os
 import shutil
 import subprocess
@@ -15,7 +17,7 @@ ASM_MIN = '    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));\n'
 
 
 @pytest.fixture(scope="module")
-def checker(tmp_path_factory):
+def build(tmp_path_factory):
     if shutil.which("g++") is None:
         pytest.skip("g++ not found")
     d = tmp_path_factory.mktemp("rayhost")
@@ -24,14 +26,30 @@ def checker(tmp_path_factory):
     src = src.replace(ASM_MIN, "    r = a < b ? a : b;\n").replace("#include <hip/hip_runtime.h>", "")
     hpp = d / "ray_host.hpp"
     hpp.write_text(src)
-    exe = d / "band_key_check"
-    subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", f'-DRAY_HPP="{hpp}"', "-o", str(exe),
-                    os.path.join(HERE, "host", "band_key_check.cpp")], check=True)
-    return str(exe)
+
+    def compile_check(name):
+        exe = d / name
+        subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", f'-DRAY_HPP="{hpp}"', "-o", str(exe),
+                        os.path.join(HERE, "host", name + ".cpp")], check=True)
+        return str(exe)
+
+    return compile_check
 
 
 @pytest.mark.parametrize("seed", [1, 2])
-def test_band_keys_exact(checker, seed):
-    out = subprocess.run([checker, str(seed), "20000"], capture_output=True, text=True)
+def test_band_keys_exact(build, seed):
+    out = subprocess.run([build("band_key_check"), str(seed), "20000"], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "mismatches 0" in out.stdout
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_tile_resume_matches_plain_walk(build, seed):
+    """The tile pass's resumed box walks (crossing counts from the binning's
+    tile walk, walk_advance, walk_enter_box, box_walk_from / box_walk_next)
+    visit exactly the plain voxel walk's voxels of each tile, in order, with
+    the same box index and distance numerator, over random rays, tilings and
+    window clips."""
+    out = subprocess.run([build("box_walk_check"), str(seed), "8000"], capture_output=True, text=True)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "mismatches 0" in out.stdout
