@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
         B.ctl->n_light = 0;
         B.ctl->entries = 0;
         B.ctl->overflow = 0;
-        for (int q = 0; q < kQueues; ++q) B.ctl->work[q] = 0;
+        for (int q = 0; q < kQueues; ++q) B.ctl->work[q * kQueueStride] = 0;
     }
     if (blockIdx.x >= H.nblocks) return;
     for (uint32_t j = threadIdx.x; j < kHashSlots; j += kBinBlock) {
@@ -637,7 +637,8 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
             }
         }
         // next tile from this workgroup's queue
-        if (threadIdx.x == 0) s_job = gridDim.x + queue + kQueues * atomicAdd(&B.ctl->work[queue], 1u);
+        if (threadIdx.x == 0)
+            s_job = gridDim.x + queue + kQueues * atomicAdd(&B.ctl->work[queue * kQueueStride], 1u);
         __syncthreads();
         job = uniform(s_job);
     }

@@ -62,12 +62,16 @@ struct BatchHdr {
 };
 
 constexpr int kQueues = 8;  // tile job queues, one per XCD (workgroup b runs on XCD b % 8)
+// Words between two queue counters: each counter on a 128-byte line of its
+// own, so that atomics on different queues do not meet in one line.
+constexpr int kQueueStride = 32;
 
 struct BatchCtl {
     uint32_t n_nonempty;  // busy tiles with heavy work, listed from the list's start
     uint32_t entries, overflow;
     uint32_t n_light;     // the other busy tiles, listed from the list's end
-    uint32_t work[kQueues];  // next job of each queue
+    uint32_t pad[28];
+    uint32_t work[kQueues * kQueueStride];  // next job of queue q: work[q * kQueueStride]
 };
 
 // Device addresses of one engine (all inside buffers the engine owns).
