@@ -223,23 +223,32 @@ __device__ __forceinline__ int32_t map_of_tile(const BatchArrays &B, int32_t nma
 // keeps them few). Four lanes share a tile, each summing a quarter of its
 // sequence slots, so that the chains of count loads stay short.
 constexpr int kAllocTiles = kAllocBlock / 4;
+constexpr int kAllocPer = kMaxSeq / 4;  // sequence slots per lane, at most
 // A tile with this many entries or more is listed first: the persistent tile
 // pass then starts the longest tiles early instead of ending on one of them.
 constexpr uint32_t kHeavyTile = 2048;
 
 __global__ __launch_bounds__(kAllocBlock) void k_alloc(BatchArrays B)
 {
-    __shared__ uint32_t s_wc[kAllocBlock / 64], s_wn[kAllocBlock / 64], s_wl[kAllocBlock / 64];
-    __shared__ uint32_t s_base_c, s_base_n, s_base_l;
+    __shared__ uint32_t s_w[3][kAllocBlock / 64];  // per wave: entries, heavy tiles, light tiles
+    __shared__ uint32_t s_base[3];
     const BatchHdr H = *B.hdr;
     if (blockIdx.x * kAllocTiles >= H.gtiles) return;
     const uint32_t t = blockIdx.x * kAllocTiles + threadIdx.x / 4;
     const uint32_t part = threadIdx.x & 3u, wave = threadIdx.x / 64;
-    const int per = (H.S + 3) / 4;
+    const int per = (H.S + 3) / 4;  // at most kAllocPer
     const int s_lo = (int)part * per, s_hi = min(H.S, s_lo + per);
+    // this part's counts, kept for the runs: every load is issued (at a
+    // clamped, valid index) before any is used, so all are in flight together
+    uint32_t cs[kAllocPer];
+    const uint32_t tc = min(t, H.gtiles - 1u);
+#pragma unroll
+    for (int j = 0; j < kAllocPer; ++j) cs[j] = B.counts[(uint32_t)min(s_lo + j, H.S - 1) * H.gtiles + tc];
+#pragma unroll
+    for (int j = 0; j < kAllocPer; ++j) cs[j] = (t < H.gtiles && s_lo + j < s_hi) ? cs[j] : 0u;
     uint32_t c = 0;
-    if (t < H.gtiles)
-        for (int sq = s_lo; sq < s_hi; ++sq) c += B.counts[(uint32_t)sq * H.gtiles + t];
+#pragma unroll
+    for (int j = 0; j < kAllocPer; ++j) c += cs[j];
     // inclusive prefix of the four parts of a tile, and the tile's total
     uint32_t pq = c;
     {
@@ -268,42 +277,40 @@ __global__ __launch_bounds__(kAllocBlock) void k_alloc(BatchArrays B)
     pn = (uint32_t)__shfl((int)pn, (int)(lane() | 3u));
     pl = (uint32_t)__shfl((int)pl, (int)(lane() | 3u));
     if (lane() == 63) {
-        s_wc[wave] = pc;
-        s_wn[wave] = pn;
-        s_wl[wave] = pl;
+        s_w[0][wave] = pc;
+        s_w[1][wave] = pn;
+        s_w[2][wave] = pl;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t sc = 0, sn = 0, sl = 0;
+    if (threadIdx.x < 3) {
+        // lane a: exclusive prefix of counter a over the waves, then one
+        // atomic for the block; the three atomics leave as one instruction
+        const int a = (int)threadIdx.x;
+        uint32_t sum = 0;
         for (int k = 0; k < kAllocBlock / 64; ++k) {
-            const uint32_t a = s_wc[k], b = s_wn[k], d = s_wl[k];
-            s_wc[k] = sc;
-            s_wn[k] = sn;
-            s_wl[k] = sl;
-            sc += a;
-            sn += b;
-            sl += d;
+            const uint32_t v = s_w[a][k];
+            s_w[a][k] = sum;
+            sum += v;
         }
-        s_base_c = sc ? atomicAdd(&B.ctl->entries, sc) : 0u;
-        s_base_n = sn ? atomicAdd(&B.ctl->n_nonempty, sn) : 0u;
-        s_base_l = sl ? atomicAdd(&B.ctl->n_light, sl) : 0u;
+        uint32_t *ctr = a == 0 ? &B.ctl->entries : (a == 1 ? &B.ctl->n_nonempty : &B.ctl->n_light);
+        s_base[a] = sum ? atomicAdd(ctr, sum) : 0u;
     }
     __syncthreads();
     if (tile_c) {
         // this part's first run: after the wave's earlier tiles and the
         // tile's earlier parts
-        uint32_t off = s_base_c + s_wc[wave] + (pc - tile_c) + (pq - c);
-        for (int sq = s_lo; sq < s_hi; ++sq) {
-            const uint32_t k = (uint32_t)sq * H.gtiles + t;
-            const uint32_t ck = B.counts[k];
-            if (!ck) continue;  // runs of empty slots are never read
+        uint32_t off = s_base[0] + s_w[0][wave] + (pc - tile_c) + (pq - c);
+#pragma unroll
+        for (int j = 0; j < kAllocPer; ++j) {
+            if (!cs[j]) continue;  // runs of empty slots are never read (nor slots past S)
+            const uint32_t k = (uint32_t)(s_lo + j) * H.gtiles + t;
             B.offsets[k] = off;
             B.cursor[k] = off;
-            off += ck;
+            off += cs[j];
         }
         if (part == 0u) {
             const uint32_t slot =
-                heavy ? s_base_n + s_wn[wave] + pn - 1u : H.gtiles - 1u - (s_base_l + s_wl[wave] + pl - 1u);
+                heavy ? s_base[1] + s_w[1][wave] + pn - 1u : H.gtiles - 1u - (s_base[2] + s_w[2][wave] + pl - 1u);
             B.nonempty[slot] = t;
             B.nonempty_map[slot] = (uint32_t)map_of_tile(B, H.nmaps, t);
         }
