@@ -32,6 +32,12 @@ constexpr int kAllocBlock = 1024;
 
 __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
 
+// A map array seen as global memory: through a generic pointer the compiler
+// must assume it may alias the LDS buffers, and it then waits for every map
+// load before the LDS store that follows it.
+typedef __attribute__((address_space(1))) int16_t glob_i16;
+__device__ __forceinline__ glob_i16 *glob(int16_t *p) { return (glob_i16 *)p; }
+
 __device__ __forceinline__ uint32_t hash_slot(uint32_t key)
 {
     return (key * 2654435761u) >> (32 - 10);  // kHashSlots = 2^10
@@ -389,6 +395,7 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) { return (uint32_t)__bui
 // LDS byte address of a shared-memory pointer, and back: an address kept
 // in one integer register needs no base added per access.
 typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+
 __device__ __forceinline__ uint32_t lds_address(uint64_t *p) { return (uint32_t)(uintptr_t)(lds_u64 *)p; }
 __device__ __forceinline__ unsigned long long *lds_pointer(int32_t a)
 {
@@ -499,8 +506,9 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                 const int32_t rx = (int32_t)(v >> (H.lt[1] + H.lt[2])) + t0[0];
                 if (rx >= MD.dims[0] || ry >= MD.dims[1] || rz >= MD.dims[2]) continue;
                 const int64_t slot = slot_of_rel(MD, rx, ry, rz);
-                c_sdf[v] = MD.sdf[slot];
-                c_w[v] = MD.w[slot];
+                const int16_t sv = glob(MD.sdf)[slot], wv = glob(MD.w)[slot];
+                c_sdf[v] = sv;
+                c_w[v] = wv;
             }
         }
         const int nbusy = (int)uniform(s_busy);
@@ -639,8 +647,8 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                 const int32_t rx = (int32_t)(v >> (H.lt[1] + H.lt[2])) + t0[0];
                 if (rx >= MD.dims[0] || ry >= MD.dims[1] || rz >= MD.dims[2]) continue;
                 const int64_t slot = slot_of_rel(MD, rx, ry, rz);
-                MD.sdf[slot] = c_sdf[v];
-                MD.w[slot] = c_w[v];
+                glob(MD.sdf)[slot] = c_sdf[v];
+                glob(MD.w)[slot] = c_w[v];
             }
         }
         // next tile from this workgroup's queue
