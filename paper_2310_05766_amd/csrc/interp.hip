@@ -238,8 +238,8 @@ __global__ __launch_bounds__(kInterpBlock) __attribute__((amdgpu_waves_per_eu(4,
         int32_t gmin = g0 < g1 ? g0 : g1, gmax = g0 < g1 ? g1 : g0;
         gmin = gmin > lo[da] ? gmin : lo[da];
         gmax = gmax < hi[da] - 1 ? gmax : hi[da] - 1;
-        const int32_t k = (gmin >> kCarveChunkLog2) + chunk;
-        const int32_t slo = k << kCarveChunkLog2, shi = slo + (1 << kCarveChunkLog2);
+        const int32_t k = (gmin >> kCarveChunkLog2) + chunk;  // arithmetic shift: floor division
+        const int32_t slo = k * (1 << kCarveChunkLog2), shi = slo + (1 << kCarveChunkLog2);
         if (gmin <= gmax && slo <= gmax) {
             lo[da] = lo[da] > slo ? lo[da] : slo;
             hi[da] = hi[da] < shi ? hi[da] : shi;
