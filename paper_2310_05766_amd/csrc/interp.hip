@@ -38,7 +38,7 @@ namespace tsdf {
 namespace {
 
 constexpr int kInterpBlock = 256;
-constexpr int kCarveChunkLog2 = 6;
+constexpr int kCarveChunkLog2 = 3;
 
 // rdiv(n, d) = sign(n) floor((2|n| + d) / 2d), to nearest with ties away
 // from zero, for a divisor 0 < d < 2^32 fixed per ray (given as 2d and
