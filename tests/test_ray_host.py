@@ -4,7 +4,10 @@ g++ compiles csrc/ray.hpp with its one inline-asm minimum replaced.
   the other walks against exact integer rounding, over band walks of random
   rays with frequent exact ties, at perturbed reciprocal estimates;
 * box_walk_check: the tile pass's resumed box walks against the plain voxel
-  walk."""
+  walk;
+* free_walk_check: carving's free-space walk, clipped to random boxes and to
+  the carving scan's slabs, against the oracle's segment voxels and keys
+  (the oracle is compiled with gcc and linked in)."""
 import os
 import shutil
 import subprocess
@@ -27,10 +30,17 @@ def build(tmp_path_factory):
     hpp = d / "ray_host.hpp"
     hpp.write_text(src)
 
-    def compile_check(name):
+    def compile_check(name, with_oracle=False):
         exe = d / name
+        extra = []
+        if with_oracle:
+            obj = d / "oracle.o"
+            if not obj.exists():
+                subprocess.run(["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-c", "-o", str(obj),
+                                os.path.join(HERE, "..", "oracle", "tsdf_oracle.c")], check=True)
+            extra = [str(obj), "-lm"]
         subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", f'-DRAY_HPP="{hpp}"', "-o", str(exe),
-                        os.path.join(HERE, "host", name + ".cpp")], check=True)
+                        os.path.join(HERE, "host", name + ".cpp"), *extra], check=True)
         return str(exe)
 
     return compile_check
@@ -51,5 +61,17 @@ def test_tile_resume_matches_plain_walk(build, seed):
     the same box index and distance numerator, over random rays, tilings and
     window clips."""
     out = subprocess.run([build("box_walk_check"), str(seed), "8000"], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "mismatches 0" in out.stdout
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_free_walk_matches_oracle(build, seed):
+    """Carving's free-space walk (LongWalk / FreeWalk) clipped to random boxes
+    and to 8-voxel slabs of a window visits exactly the oracle's voxels of the
+    segment [o, S] in that box, in order, with the oracle's keys; the slabs
+    together give the segment's voxels in the window."""
+    out = subprocess.run([build("free_walk_check", with_oracle=True), str(seed), "3000"], capture_output=True,
+                         text=True)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "mismatches 0" in out.stdout
