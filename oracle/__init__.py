@@ -62,7 +62,7 @@ def lib():
         L.or_integrate.restype = C.c_int
         L.or_integrate.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int64, C.POINTER(C.c_double), i64p]
         L.or_volume.restype = C.c_int
-        L.or_volume.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int64, C.POINTER(C.c_double),
+        L.or_volume.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int64, C.POINTER(C.c_double), i64p,
                                 C.POINTER(C.c_uint64)]
         L.or_shift.restype = C.c_int
         L.or_shift.argtypes = [C.c_void_p, i32p]
@@ -269,12 +269,20 @@ class OracleMap:
             raise ValueError(f"oracle integrate failed ({rc})")
         return dict(points_in=int(st[0]), points_valid=int(st[1]), visits=int(st[2]), voxels_updated=int(st[3]))
 
-    def volume(self, xyz, pose) -> np.ndarray:
-        """Per-scan candidate keys over the window in slot order (uint64)."""
+    def volume(self, xyz, pose, order=None) -> np.ndarray:
+        """Per-scan candidate keys over the window in slot order (uint64).
+        order: optional permutation of the rows, the order in which the
+        points are taken (each keeps its row as its index)."""
         x = np.ascontiguousarray(np.asarray(xyz, dtype=np.float32).reshape(-1, 3))
         M = np.ascontiguousarray(np.asarray(pose, dtype=np.float64).reshape(16))
         out = np.empty(int(np.prod(self.dims)), dtype=np.uint64)
-        rc = lib().or_volume(self._m, _p(x, C.c_float), x.shape[0], _p(M, C.c_double), _p(out, C.c_uint64))
+        op = None
+        if order is not None:
+            oa = np.ascontiguousarray(np.asarray(order, dtype=np.int64))
+            if oa.shape != (x.shape[0],):
+                raise ValueError("order must hold one index per point")
+            op = _p(oa, C.c_int64)
+        rc = lib().or_volume(self._m, _p(x, C.c_float), x.shape[0], _p(M, C.c_double), op, _p(out, C.c_uint64))
         if rc != 0:
             raise ValueError(f"oracle volume failed ({rc})")
         return out.reshape(self.dims)

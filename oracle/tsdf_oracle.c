@@ -276,9 +276,9 @@ uint64_t or_key(int64_t s, uint64_t i)
 int64_t or_interp_delta(double vfov_deg, int32_t hlines)
 {
     if (!(vfov_deg > 0.0) || !isfinite(vfov_deg) || hlines < 1) return 0;
-    const double step = vfov_deg / (double)hlines;
-    if (!(step < 45.0)) return 0;
-    return (int64_t)llrint(tan(step * (M_PI / 180.0)) * 1048576.0);
+    const double angle_deg = vfov_deg / (double)hlines; /* between neighbouring lines */
+    if (!(angle_deg < 45.0)) return 0;
+    return (int64_t)llrint(tan(angle_deg * (M_PI / 180.0)) * 1048576.0);
 }
 
 /* The sensor's up vector (its z axis in the world frame, column 2 of the
@@ -286,6 +286,15 @@ int64_t or_interp_delta(double vfov_deg, int32_t hlines)
 void or_up_vector(const double M[16], int64_t U[3])
 {
     for (int a = 0; a < 3; ++a) U[a] = (int64_t)llrint(M[4 * a + 2] * 1024.0);
+}
+
+/* out = a x b, component k = a[k+1] b[k+2] - a[k+2] b[k+1] (indices mod 3) */
+static void cross3(const int64_t a[3], const int64_t b[3], int64_t out[3])
+{
+    for (int k = 0; k < 3; ++k) {
+        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+        out[k] = a[k1] * b[k2] - a[k2] * b[k1];
+    }
 }
 
 /* The fill offset e of one band voxel g of a ray (q, D, r): the paper fills
@@ -309,12 +318,8 @@ void or_fill_offset(const int64_t q[3], const int64_t o[3], const int64_t D[3], 
     const int64_t rr = (int64_t)r;
     int64_t d[3], w[3], v[3];
     for (int a = 0; a < 3; ++a) d[a] = or_rdiv(1024 * D[a], rr);
-    w[0] = d[1] * U[2] - d[2] * U[1];
-    w[1] = d[2] * U[0] - d[0] * U[2];
-    w[2] = d[0] * U[1] - d[1] * U[0];
-    v[0] = d[1] * w[2] - d[2] * w[1];
-    v[1] = d[2] * w[0] - d[0] * w[2];
-    v[2] = d[0] * w[1] - d[1] * w[0];
+    cross3(d, U, w); /* d x up */
+    cross3(d, w, v); /* d x (d x up) */
     const int64_t nv = (int64_t)or_isqrt((uint64_t)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
     if (nv == 0) return;
     int64_t proj = 0; /* (c - o) . D */
@@ -370,12 +375,13 @@ static int in_window(const int32_t origin[3], const int32_t dims[3], const int64
     return 1;
 }
 
+/* Bucket of a chunk key: the spatial hash of Teschner et al. (2003,
+ * "Optimized Spatial Hashing for Collision Detection of Deformable Objects"):
+ * the xor of the coordinates times three large primes. It only places chunks
+ * in the open-addressing table; no voxel value depends on it. */
 static uint64_t hash3(const int64_t k[3])
 {
-    uint64_t h = (uint64_t)k[0] * 0x9E3779B97F4A7C15ULL;
-    h ^= (uint64_t)k[1] * 0xC2B2AE3D27D4EB4FULL + (h << 6) + (h >> 2);
-    h ^= (uint64_t)k[2] * 0x165667B19E3779F9ULL + (h << 6) + (h >> 2);
-    return h;
+    return ((uint64_t)k[0] * 73856093u) ^ ((uint64_t)k[1] * 19349663u) ^ ((uint64_t)k[2] * 83492791u);
 }
 
 static chunk_t *store_find(omap *m, const int64_t k[3], int create)
@@ -500,7 +506,8 @@ void or_map_destroy(omap *m)
 /* Per-scan volume V (candidates only, no merge): for every point i with a
  * ray, for every voxel g of its band segment inside the window,
  * K[g] = min(K[g], key(s, i)). stats: points_valid, visits. */
-static int build_volume(omap *m, const float *xyz, int64_t n, const double M[16], int64_t *valid, int64_t *visits)
+static int build_volume(omap *m, const float *xyz, int64_t n, const double M[16], const int64_t *order,
+                        int64_t *valid, int64_t *visits)
 {
     int64_t o[3];
     if (!or_quantise_origin(M, m->scale, o)) return OR_EINVAL;
@@ -514,7 +521,10 @@ static int build_volume(omap *m, const float *xyz, int64_t n, const double M[16]
     or_up_vector(M, U);
     *valid = 0;
     *visits = 0;
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t k = 0; k < n; ++k) {
+        /* point i keeps its index (its row) whatever order the points are
+         * taken in: the per-voxel minimum of Sec. VI does not depend on it */
+        const int64_t i = order ? order[k] : k;
         int64_t q[3], D[3], S[3], E[3];
         uint64_t r;
         if (!or_quantise_point(&xyz[3 * i], M, m->scale, q)) continue;
@@ -635,7 +645,7 @@ int or_integrate(omap *m, const float *xyz, int64_t n, const double M[16], int64
     int64_t o[3];
     if (!or_quantise_origin(M, m->scale, o)) return OR_EINVAL;
     int64_t valid = 0, visits = 0;
-    int rc = build_volume(m, xyz, n, M, &valid, &visits);
+    int rc = build_volume(m, xyz, n, M, NULL, &valid, &visits);
     if (rc != OR_OK) return rc;
     int64_t U = merge_volume(m);
     if (stats) {
@@ -648,12 +658,24 @@ int or_integrate(omap *m, const float *xyz, int64_t n, const double M[16], int64
 }
 
 /* The per-scan volume V alone, as keys over the window in slot order
- * (EMPTY where no ray reached), without touching the map. */
-int or_volume(omap *m, const float *xyz, int64_t n, const double M[16], uint64_t *keys_out)
+ * (EMPTY where no ray reached), without touching the map. order (nullable):
+ * a permutation of 0..n-1, the order in which the points are taken; each
+ * point keeps its row as its index. */
+int or_volume(omap *m, const float *xyz, int64_t n, const double M[16], const int64_t *order, uint64_t *keys_out)
 {
     if (!m || n < 0 || !M || !keys_out) return OR_EINVAL;
+    if (order) {
+        /* a permutation: every row exactly once */
+        unsigned char *seen = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+        if (!seen) return OR_ENOMEM;
+        for (int64_t k = 0; k < n; ++k) {
+            if (order[k] < 0 || order[k] >= n || seen[order[k]]) { free(seen); return OR_EINVAL; }
+            seen[order[k]] = 1;
+        }
+        free(seen);
+    }
     int64_t valid, visits;
-    int rc = build_volume(m, xyz, n, M, &valid, &visits);
+    int rc = build_volume(m, xyz, n, M, order, &valid, &visits);
     if (rc != OR_OK) return rc;
     memcpy(keys_out, m->K, (size_t)m->nvox * sizeof(uint64_t));
     for (int64_t t = 0; t < m->ntouched; ++t) m->K[m->touched[t]] = KEY_EMPTY;
@@ -753,11 +775,14 @@ static const int kTets[6][4] = {{0, 1, 3, 7}, {0, 3, 2, 7}, {0, 2, 6, 7}, {0, 6,
 
 static void edge_point(const int64_t g[3], int a, int b, const int64_t s[8], double vs, float *out)
 {
-    const double t = (double)s[a] / ((double)s[a] - (double)s[b]);
+    /* s_a - s_b is an exact integer (|s| < 2^15) */
+    const double t = (double)s[a] / (double)(s[a] - s[b]);
     for (int k = 0; k < 3; ++k) {
-        const double ga = (double)(g[k] + ((a >> k) & 1)) + 0.5;
-        const double gb = (double)(g[k] + ((b >> k) & 1)) + 0.5;
-        out[k] = (float)((ga + t * (gb - ga)) * vs);
+        const int bit_a = (a >> k) & 1, bit_b = (b >> k) & 1;
+        /* centre of corner a along axis k, and the edge's direction (-1, 0, 1) */
+        const double centre_a = (double)g[k] + (double)bit_a + 0.5;
+        const double dir = (double)(bit_b - bit_a);
+        out[k] = (float)((centre_a + t * dir) * vs);
     }
 }
 
@@ -787,34 +812,40 @@ int64_t or_mesh(omap *m, const int32_t lo[3], const int32_t hi[3], float *out, i
                         in[k] = s[v[k]] < 0;
                         nin += in[k];
                     }
-                    if (nin == 0 || nin == 4) continue;
+                    if (nin % 4 == 0) continue; /* all inside or all outside: no surface */
                     float tri[2][9];
                     int ntri;
                     if (nin == 1 || nin == 3) {
-                        /* the lone vertex (inside when nin == 1, outside when 3) */
+                        /* the lone vertex: the only inside one (nin == 1) or
+                         * the only outside one (nin == 3) */
+                        const int lone_is_inside = nin == 1;
                         int lone = 0;
                         for (int k = 0; k < 4; ++k)
-                            if (in[k] == (nin == 1)) lone = k;
+                            if (in[k] == lone_is_inside) lone = k;
                         int e = 0;
                         for (int k = 0; k < 4; ++k)
                             if (k != lone) edge_point(g, v[lone], v[k], s, m->voxel_size, &tri[0][3 * e++]);
                         ntri = 1;
                     } else {
-                        /* two inside (i0 < i1), two outside (o0 < o1): the quad
-                         * i0o0, i0o1, i1o1, i1o0 as two triangles */
-                        int i0 = -1, i1 = -1, o0 = -1, o1 = -1;
+                        /* two inside (ins[0] < ins[1]), two outside (outs[0] <
+                         * outs[1]): the quad i0o0, i0o1, i1o1, i1o0 as the two
+                         * triangles (i0o0, i0o1, i1o1) and (i0o0, i1o1, i1o0) */
+                        int ins[2], outs[2], ni = 0, no = 0;
                         for (int k = 0; k < 4; ++k) {
-                            if (in[k]) { if (i0 < 0) i0 = k; else i1 = k; }
-                            else { if (o0 < 0) o0 = k; else o1 = k; }
+                            if (in[k]) ins[ni++] = k;
+                            else outs[no++] = k;
                         }
-                        float q[4][3];
-                        edge_point(g, v[i0], v[o0], s, m->voxel_size, q[0]);
-                        edge_point(g, v[i0], v[o1], s, m->voxel_size, q[1]);
-                        edge_point(g, v[i1], v[o1], s, m->voxel_size, q[2]);
-                        edge_point(g, v[i1], v[o0], s, m->voxel_size, q[3]);
-                        const int order[6] = {0, 1, 2, 0, 2, 3};
-                        for (int k = 0; k < 6; ++k)
-                            for (int a = 0; a < 3; ++a) tri[k / 3][3 * (k % 3) + a] = q[order[k]][a];
+                        float p00[3], p01[3], p11[3], p10[3];
+                        edge_point(g, v[ins[0]], v[outs[0]], s, m->voxel_size, p00);
+                        edge_point(g, v[ins[0]], v[outs[1]], s, m->voxel_size, p01);
+                        edge_point(g, v[ins[1]], v[outs[1]], s, m->voxel_size, p11);
+                        edge_point(g, v[ins[1]], v[outs[0]], s, m->voxel_size, p10);
+                        memcpy(&tri[0][0], p00, sizeof p00);
+                        memcpy(&tri[0][3], p01, sizeof p01);
+                        memcpy(&tri[0][6], p11, sizeof p11);
+                        memcpy(&tri[1][0], p00, sizeof p00);
+                        memcpy(&tri[1][3], p11, sizeof p11);
+                        memcpy(&tri[1][6], p10, sizeof p10);
                         ntri = 2;
                     }
                     for (int k = 0; k < ntri; ++k) {
@@ -864,19 +895,24 @@ int or_reg_point(omap *m, const float p[3], const double M[16], double *phi, dou
         if (sq <= -m->tau_u || sq >= m->tau_u) return 0;
         c[k] = (double)sq * m->voxel_size / 1024.0; /* metres */
     }
-    /* trilinear value and its derivatives along x, y, z (per voxel) */
-    const double c00 = c[0] + f[0] * (c[1] - c[0]), c10 = c[2] + f[0] * (c[3] - c[2]);
-    const double c01 = c[4] + f[0] * (c[5] - c[4]), c11 = c[6] + f[0] * (c[7] - c[6]);
-    const double c0 = c00 + f[1] * (c10 - c00), c1 = c01 + f[1] * (c11 - c01);
-    *phi = c0 + f[2] * (c1 - c0);
-    const double dx0 = (c[1] - c[0]) + f[1] * ((c[3] - c[2]) - (c[1] - c[0]));
-    const double dx1 = (c[5] - c[4]) + f[1] * ((c[7] - c[6]) - (c[5] - c[4]));
-    const double dx = dx0 + f[2] * (dx1 - dx0);
-    const double dy = (c10 - c00) + f[2] * ((c11 - c01) - (c10 - c00));
-    const double dz = c1 - c0;
-    grad[0] = dx / m->voxel_size;
-    grad[1] = dy / m->voxel_size;
-    grad[2] = dz / m->voxel_size;
+    /* the trilinear interpolant by its definition: corner k has weight
+     * prod_a (f_a if bit a of k is set, else 1 - f_a); its derivative along
+     * axis b replaces factor b by +1 or -1 (per voxel, then per metre) */
+    double val = 0.0, dval[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < 8; ++k) {
+        double fac[3], dfac[3];
+        for (int a = 0; a < 3; ++a) {
+            const int bit = (k >> a) & 1;
+            fac[a] = bit ? f[a] : 1.0 - f[a];
+            dfac[a] = bit ? 1.0 : -1.0;
+        }
+        val += c[k] * (fac[0] * fac[1] * fac[2]);
+        dval[0] += c[k] * (dfac[0] * fac[1] * fac[2]);
+        dval[1] += c[k] * (fac[0] * dfac[1] * fac[2]);
+        dval[2] += c[k] * (fac[0] * fac[1] * dfac[2]);
+    }
+    *phi = val;
+    for (int a = 0; a < 3; ++a) grad[a] = dval[a] / m->voxel_size;
     for (int a = 0; a < 3; ++a) wout[a] = w[a];
     return 1;
 }
@@ -933,7 +969,8 @@ int or_reg_step(const double sums[29], double lambda, const double M[16], double
         for (int q = 0; q < i; ++q) acc -= L[i][q] * yv[q];
         yv[i] = acc / L[i][i];
     }
-    for (int i = 5; i >= 0; --i) {
+    for (int back = 0; back < 6; ++back) { /* rows 5, 4, ..., 0 */
+        const int i = 5 - back;
         double acc = yv[i];
         for (int q = i + 1; q < 6; ++q) acc -= L[q][i] * d[q];
         d[i] = acc / L[i][i];
@@ -980,7 +1017,9 @@ int or_register(omap *m, const float *xyz, int64_t n, const double M0[16], int32
         double Mn[16];
         if (!or_reg_step(sums, lambda, M, Mn, d)) break;
         memcpy(M, Mn, sizeof(M));
-        step = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + d[3] * d[3] + d[4] * d[4] + d[5] * d[5]);
+        double ss = 0.0;
+        for (int a = 0; a < 6; ++a) ss += d[a] * d[a];
+        step = sqrt(ss);
     }
     or_reg_sums(m, xyz, n, M, sums);
     memcpy(Mout, M, sizeof(M));

@@ -68,6 +68,27 @@ def test_quantise_random_poses_match_exact_fma():
         assert list(o) == [round(M[a][3] * scale) for a in range(3)]
 
 
+def test_quantise_fma_chain_crafted_rounding():
+    """A case built so that the fused chain and separately rounded products
+    land on different sides of a rounding boundary: with x = 1 + 2^-23 and
+    M[0][0] = 1 + 2^-30, the exact product carries a 2^-53 term that a
+    separate multiply drops (a tie, to even), and the translation cancels
+    everything else to 2^-11. The chain gives w = 2^-11 + 2^-53, so at
+    1024 units per metre q_x = rint(0.5 + 2^-43) = 1; unfused it would be
+    rint(0.5) = 0."""
+    x = 1.0 + 2.0 ** -23
+    assert float(np.float32(x)) == x
+    M = np.eye(4)
+    M[0, 0] = 1.0 + 2.0 ** -30
+    M[0, 3] = -(1.0 + 2.0 ** -23 + 2.0 ** -30) + 2.0 ** -11
+    assert Fraction(M[0, 3]) == -(1 + Fraction(1, 2 ** 23) + Fraction(1, 2 ** 30)) + Fraction(1, 2 ** 11)
+    p = np.array([x, 0.0, 0.0], dtype=np.float32)
+    assert brute.quantise(p, M, 1024.0)[0] == 1
+    assert oracle.quantise_point(p, M, 1024.0)[0] == 1
+    unfused = M[0, 0] * x + M[0, 3]  # two roundings
+    assert round(unfused * 1024.0) == 0
+
+
 def test_quantise_half_even_and_range():
     # w * scale = 2.5 exactly -> 2 (half to even); 3.5 -> 4
     M = np.eye(4)
@@ -201,6 +222,35 @@ def test_volume_vs_brute_force(seed):
                 else:
                     assert kk == 0xFFFFFFFFFFFFFFFF
     assert seen > 50
+    m.close()
+
+
+def test_volume_permutation_invariance():
+    """Sec. VI keeps, per voxel, the smallest distance over all rays of a
+    scan; with ties broken by the point index (reading 1) the result cannot
+    depend on the order in which the rays are taken. Points taken in
+    reverse and in shuffled orders (each keeping its row as its index) give
+    the identical volume, on a room scan with index ties, NaN rows and many
+    voxels reached by several rays."""
+    w1 = synth.config1()
+    spec = w1.maps[0]
+    xyz = w1.scans[0].xyz[::4].copy()
+    n = xyz.shape[0]
+    xyz[n // 3:n // 3 + 40] = xyz[:40]  # duplicates: equal |s| from different rows
+    xyz[7::97] = np.nan
+    pose = synth.fuzz_pose(61, max_t=0.3)
+    m = oracle.OracleMap.from_spec(spec)
+    ref = m.volume(xyz, pose)
+    assert np.array_equal(m.volume(xyz, pose, order=np.arange(n)), ref)
+    g = np.random.default_rng(61)
+    orders = [np.arange(n)[::-1], g.permutation(n), g.permutation(n)]
+    for order in orders:
+        assert np.array_equal(m.volume(xyz, pose, order=order), ref)
+    # the volume holds ties between rows: the index part of the key decides
+    reached = ref[ref != np.uint64(0xFFFFFFFFFFFFFFFF)]
+    assert reached.size > 10000
+    with pytest.raises(ValueError):
+        m.volume(xyz, pose, order=np.zeros(n, np.int64))  # not a permutation
     m.close()
 
 
@@ -379,6 +429,147 @@ def test_interp_delta_eq3():
         assert oracle.interp_delta(vfov, lines) == 0  # invalid, or angle >= 45 deg
 
 
+def _exact_q20(num_terms):
+    """round-half-even(2^20 x) for x = sum of c * sqrt(k) terms, evaluated
+    with integer square roots at 2^-80 precision (no trigonometry)."""
+    P = 80
+    acc = 0
+    for c, k in num_terms:
+        acc += Fraction(c) * Fraction(math.isqrt(k << (2 * P)), 1 << P)
+    return acc * 2 ** 20
+
+
+def test_interp_delta_closed_form_surds():
+    """Eq. (3) at angles whose tangent is a known surd: tan 30 = 1/sqrt 3,
+    tan 22.5 = sqrt 2 - 1, tan 15 = 2 - sqrt 3, tan 7.5 = sqrt 6 - sqrt 3 +
+    sqrt 2 - 2. Values in 1/2^20 units against the exact rounding, with no
+    trigonometric function on the checking side."""
+    cases = [
+        ((60.0, 2), [(Fraction(1, 3), 3)]),                      # 30 deg
+        ((90.0, 4), [(1, 2), (-1, 1)]),                          # 22.5 deg
+        ((45.0, 3), [(2, 1), (-1, 3)]),                          # 15 deg
+        ((30.0, 4), [(1, 6), (-1, 3), (1, 2), (-2, 1)]),         # 7.5 deg
+        ((120.0, 4), [(Fraction(1, 3), 3)]),                     # 30 deg again
+    ]
+    for (vfov, lines), terms in cases:
+        got = oracle.interp_delta(vfov, lines)
+        x = _exact_q20(terms)
+        lo = math.floor(x)
+        assert abs(x - lo - Fraction(1, 2)) > Fraction(1, 10 ** 6)  # not near a tie
+        assert got == (lo + 1 if x - lo > Fraction(1, 2) else lo), (vfov, lines, got, float(x))
+    # a wrong unit (degrees taken as radians) or hlines - 1 would move these far
+    assert oracle.interp_delta(60.0, 2) != oracle.interp_delta(60.0, 3)
+
+
+def _rot_x(deg):
+    c, s = math.cos(math.radians(deg)), math.sin(math.radians(deg))
+    M = np.eye(4)
+    M[:3, :3] = [[1, 0, 0], [0, c, -s], [0, s, c]]
+    return M
+
+
+# sensor x -> world +y, sensor y -> world +z, sensor z (up) -> world +x: an
+# exact rotation whose column 2 and row 2 differ
+_R_YZX = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+
+
+def test_up_vector_rotated_poses_closed_form():
+    """The sensor's up vector is its z axis seen in the world frame (reading
+    25): rolled 90 degrees about x it is world -y; under the rotation with
+    sensor z -> world x it is world +x. Row 2 of these rotations is (0, 1, 0)
+    in both cases, so taking a row for the column fails here."""
+    M = _rot_x(90.0)
+    M[:3, 3] = [1.25, -3.5, 0.75]
+    assert oracle.up_vector(M) == (0, -1024, 0)
+    M2 = np.eye(4)
+    M2[:3, :3] = _R_YZX
+    M2[:3, 3] = [-2.0, 4.0, 1.0]
+    assert oracle.up_vector(M2) == (1024, 0, 0)
+    # tilted 30 degrees about x: up = (0, -sin 30, cos 30) in 1/1024 units
+    M3 = _rot_x(30.0)
+    assert oracle.up_vector(M3) == (0, -512, round(1024 * math.sqrt(3) / 2))
+
+
+def test_up_vector_is_the_image_of_the_sensor_z_axis():
+    """For random poses, U is within one unit of q(p = (0, 0, 1 m)) - o at
+    1 m voxels: the pinned transform (exact-fma emulation) of the sensor's z
+    axis, minus the sensor position, i.e. 1024 R e_z up to two roundings."""
+    scale = 1024.0
+    for it in range(300):
+        M = synth.fuzz_pose((71, it), max_t=3.0)
+        q = brute.quantise((0.0, 0.0, 1.0), M, scale)
+        o = [round(M[a][3] * scale) for a in range(3)]
+        U = oracle.up_vector(M)
+        for a in range(3):
+            assert abs(U[a] - (q[a] - o[a])) <= 1, (it, U, q, o)
+
+
+def test_fill_offset_under_a_roll_closed_form():
+    """Sensor rolled 90 degrees about x (up = world -y): a ray along the
+    sensor's x axis (world +x) is filled along world y, e = (0, +h, 0), the
+    interpolation vector d x (d x up) pointing against up, with h from
+    Eq. (4). With up taken from the wrong axis this sign flips (or the fill
+    vanishes)."""
+    M = _rot_x(90.0)
+    U = oracle.up_vector(M)
+    dq = oracle.interp_delta(45.0, 128)
+    o = [512, 1536, -512]
+    for dist in (5 * 1024 + 100, 300 * 1024 + 7):
+        q = [o[0] + dist, o[1], o[2]]
+        D = [dist, 0, 0]
+        for k in (-2, 0, 3):
+            g = [q[0] // 1024 + k, o[1] // 1024, o[2] // 1024]
+            length = 1024 * g[0] + 512 - o[0]
+            h = min(_round_half_away(Fraction(dq * length, 2 ** 20)), 65535) if length > 0 else 0
+            assert oracle.fill_offset(q, o, D, dist, U, g, dq) == (0, h, 0)
+
+
+def test_interp_volume_rotated_sensor_closed_form():
+    """One ray along the sensor's x axis under the exact rotation sensor x ->
+    world +y, sensor z -> world +x: the band lies along world y with the
+    plane profile, and every band voxel fills its run along world x (up),
+    from floor((c_x - h) / 1024) to floor((c_x + h) / 1024); the smallest
+    |s| wins where runs meet."""
+    dq = oracle.interp_delta(40.0, 4)  # tan(10 deg)
+    tau = 3072
+    dims, origin = (24, 40, 8), (-12, 0, 0)
+    m = oracle.OracleMap(dims, origin, 1.0, tau, 64)
+    m.set_interpolation(dq=dq)
+    pose = np.eye(4)
+    pose[:3, :3] = _R_YZX
+    pose[:3, 3] = [0.5, 0.5, 4.5]
+    Y = 30.2
+    xyz = np.array([[Y - 0.5, 0.0, 0.0]], dtype=np.float32)  # sensor x
+    keys = m.volume(xyz, pose)
+    oy = 512
+    qy = int(round(float(np.float32(Y - 0.5)) * 1024)) + 512
+    expect = {}
+    for gy in range((qy - tau) // 1024, (qy + tau) // 1024 + 1):
+        cy = 1024 * gy + 512
+        s = max(-tau, min(tau, qy - cy))
+        h = min(_round_half_away(Fraction(dq * (cy - oy), 2 ** 20)), 65535)
+        cx = 512
+        for gx in range((cx - h) // 1024, (cx + h) // 1024 + 1):
+            if not (-12 <= gx < 12):
+                continue
+            key = (abs(s) << 48) | (s & 0xFFFF)
+            expect[(gx, gy, 4)] = min(expect.get((gx, gy, 4), 1 << 64), key)
+    assert len(expect) > 20 and any(gx < 0 for gx, _, _ in expect)
+    for gx in range(-12, 12):
+        for gy in range(40):
+            for gz in range(8):
+                kk = int(keys[gx % 24, gy % 40, gz % 8])
+                assert kk == expect.get((gx, gy, gz), 0xFFFFFFFFFFFFFFFF), (gx, gy, gz)
+    m.close()
+
+
+def _up_of(M):
+    """The sensor's z axis in the world in 1/1024 units, half to even, from
+    the rotation applied to e_z (the definition; not the oracle's code)."""
+    v = np.asarray(M, dtype=np.float64)[:3, :3] @ np.array([0.0, 0.0, 1.0])
+    return tuple(int(x) for x in np.rint(1024.0 * v))
+
+
 def test_fill_offset_axis_rays_closed_form():
     """Identity pose (up = +z): a ray along x or y is filled straight down and
     up, e = (0, 0, -h) with h = delta_z * (distance of the voxel centre along
@@ -415,7 +606,8 @@ def test_fill_offset_geometry_random():
     checked = 0
     for it in range(400):
         M = synth.fuzz_pose((41, it), max_t=2.0)
-        U = oracle.up_vector(M)
+        U = _up_of(M)
+        assert U == oracle.up_vector(M)
         o = [int(v) for v in g.integers(-50000, 50000, size=3)]
         D = [int(v) for v in g.integers(-400000, 400000, size=3)]
         q = [o[a] + D[a] for a in range(3)]
@@ -509,7 +701,7 @@ def test_interp_volume_vs_brute_force(seed):
     m.set_interpolation(dq=dq)
     keys = m.volume(xyz, M)
     o = oracle.quantise_origin(M, scale)
-    U = oracle.up_vector(M)
+    U = _up_of(M)  # the definition, so that the oracle's own up vector is checked too
     best = {}
     for i, p in enumerate(xyz):
         q = oracle.quantise_point(p, M, scale)
