@@ -226,6 +226,14 @@ tsdf_status tsdf_map_set_carving(tsdf_map *m, int32_t on);
 /* 1 when carving is on, else 0. */
 tsdf_status tsdf_map_get_carving(const tsdf_map *m, int32_t *on);
 
+/* The number of 64-bit atomicMin operations the key-volume paths
+ * (interpolation, carving) of this map have issued on its key volume since
+ * the previous call (or since the key volume was allocated), then restarts
+ * the count. These paths skip an atomic that could not lower the key it
+ * read, so the count is at most the visits. Waits for the map's stream;
+ * 0 for a map that never used the key volume. */
+tsdf_status tsdf_map_key_atomics(tsdf_map *m, int64_t *issued);
+
 /* Point-to-TSDF registration (the paper's stated next step, Sec. VIII;
  * HATSDF localises directly in its TSDF, Sec. I). A scan point p lands at
  * w = R p + t (float64, the integration's fma chain, metres); its residual
@@ -284,18 +292,6 @@ tsdf_status tsdf_map_set_tiling(tsdf_map *m, const int32_t log2_tile[3], int32_t
 tsdf_status tsdf_map_get_tiling(const tsdf_map *m, int32_t log2_tile[3], int32_t *tile_workgroups);
 tsdf_status tsdf_profile_read(tsdf_map *m, int32_t kernel, double *total_ms, int64_t *launches);
 const char *tsdf_kernel_name(int32_t kernel);
-
-/* Measurement aid, not part of the method: the device's rate for scattered
- * 64-bit atomicMin, which bounds the key-volume paths (interpolation and
- * carving). waves (a multiple of 4) wavefronts of 64 lanes each apply
- * per_lane atomicMins to pseudo-random keys of the caller's device buffer of
- * n_keys uint64, whose contents it overwrites with arbitrary values:
- * pattern 0 spreads them over the whole buffer, pattern 1 over its first
- * 2^19 keys (4 MiB, L2-resident; needs n_keys >= 2^19). Synchronous: times
- * the launch with events on hip_stream and returns the milliseconds in
- * ms_out. TSDF_EINVAL on bad arguments, TSDF_EDEVICE on a HIP error. */
-tsdf_status tsdf_atomic_probe(void *keys_dev, int64_t n_keys, int32_t waves, int32_t per_lane, int32_t pattern,
-                              void *hip_stream, float *ms_out);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,7 @@ EXPORTS = (
     "tsdf_map_get_tiling", "tsdf_batch_release", "tsdf_set_graph_launch", "tsdf_batch_profile",
     "tsdf_batch_profile_read", "tsdf_map_set_interpolation", "tsdf_map_get_interpolation", "tsdf_mesh",
     "tsdf_register_scan", "tsdf_register_sums", "tsdf_map_set_carving", "tsdf_map_get_carving",
-    "tsdf_atomic_probe",
+    "tsdf_map_key_atomics",
 )
 KERNELS = {"k_bin": 0, "k_tile": 1, "k_pack": 2, "k_unpack": 3}
 
@@ -98,8 +98,8 @@ def lib():
     L.tsdf_map_set_carving.argtypes = [vp, C.c_int32]
     L.tsdf_map_get_carving.restype = st
     L.tsdf_map_get_carving.argtypes = [vp, C.POINTER(C.c_int32)]
-    L.tsdf_atomic_probe.restype = st
-    L.tsdf_atomic_probe.argtypes = [vp, i64, C.c_int32, C.c_int32, C.c_int32, vp, C.POINTER(C.c_float)]
+    L.tsdf_map_key_atomics.restype = st
+    L.tsdf_map_key_atomics.argtypes = [vp, C.POINTER(C.c_int64)]
     L.tsdf_integrate_batch.restype = st
     L.tsdf_integrate_batch.argtypes = [C.POINTER(ScanDesc), C.c_int32, C.c_int, vp, C.POINTER(ScanStats)]
     L.tsdf_status_string.restype = C.c_char_p

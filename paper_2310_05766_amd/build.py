@@ -1,4 +1,6 @@
-"""Build the HIP library (gfx950) in-tree: paper_2310_05766_amd/libtsdf.so."""
+"""Build the HIP libraries (gfx950) in-tree: paper_2310_05766_amd/libtsdf.so
+(the TSDF library) and paper_2310_05766_amd/probe/libtsdf_probe.so (the
+benchmark's atomic-rate probe, a library of its own)."""
 from __future__ import annotations
 
 import glob
@@ -8,6 +10,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtsdf.so")
+PROBE_SRC = os.path.join(HERE, "probe", "atomic_probe.hip")
+PROBE_LIB = os.path.join(HERE, "probe", "libtsdf_probe.so")
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -39,6 +43,12 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    ptmp = PROBE_LIB + ".tmp"
+    pcmd = [hipcc, *HIPCC_FLAGS, "-o", ptmp, PROBE_SRC]
+    if verbose:
+        print(" ".join(pcmd), flush=True)
+    subprocess.check_call(pcmd)
+    os.replace(ptmp, PROBE_LIB)
     return LIB
 
 

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
     __shared__ uint32_t h_key[kHashSlots];  // key + 1; 0 = free
     __shared__ uint32_t h_cnt[kHashSlots];
     __shared__ uint32_t h_base[kFill ? kHashSlots : 1];
-    // per emitted entry: hash slot | crossing counts << 10, and rank
+    // per emitted entry: hash slot | crossing counts (7 bits per axis) << 10, and rank
     __shared__ uint32_t s_slot[kFill ? kMaxEmit * kBinBlock : 1];
     __shared__ uint16_t s_rank[kFill ? kMaxEmit * kBinBlock : 1];
     __shared__ uint32_t s_valid;
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
             if (slot != 0xffffu && (!kFill || ne < kMaxEmit)) {
                 const uint32_t rank = atomicAdd(&h_cnt[slot], 1u);
                 if (kFill) {
-                    s_slot[ne * kBinBlock + threadIdx.x] = slot | cpack << 10;
+                    s_slot[ne * kBinBlock + threadIdx.x] = slot | counts_8to7(cpack) << 10;
                     s_rank[ne * kBinBlock + threadIdx.x] = (uint16_t)rank;
                 }
             } else if (kFill) {  // table full or very long band: straight to the tile's run
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
         const uint32_t pos = h_base[sc & 1023u] + s_rank[k * kBinBlock + threadIdx.x];
         if (pos < H.cap) {
             B.entries[pos] = rec;
-            B.entries2[pos] = entry_ray(R, sc >> 10);
+            B.entries2[pos] = entry_ray(R, counts_7to8(sc >> 10));
         } else {
             atomicOr(&B.ctl->overflow, 1u);
         }
@@ -431,8 +431,9 @@ __device__ __forceinline__ MapDev uniform_map(const MapDev &m)
 }
 
 // Persistent tile pass. Workgroup b first takes busy tile b, then pulls
-// further tiles from queue b % 8 (one queue per XCD keeps same-address
-// atomics spread). Per tile, the busy sequence slots are taken in groups of
+// further tiles from queue b % nq, nq = min(8, workgroups) (one queue per
+// XCD keeps same-address atomics spread; with fewer than 8 workgroups each
+// queue still has one, so every job is reached). Per tile, the busy sequence slots are taken in groups of
 // G: the candidates of a group's runs are computed together, one LDS key
 // buffer per slot, then each voxel applies the group's scans in submission
 // order. A tile busy in several slots keeps its SDF and weights in LDS.
@@ -461,7 +462,8 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
     const int32_t shb[3] = {sh[0] + 3, sh[1] + 3, 3};          // the same, in bytes of 8-byte keys
     uint32_t job = blockIdx.x;
     if (job >= nne) return;
-    const uint32_t queue = blockIdx.x % kQueues;
+    const uint32_t nq = gridDim.x < (uint32_t)kQueues ? gridDim.x : (uint32_t)kQueues;
+    const uint32_t queue = blockIdx.x % nq;
     for (uint32_t v = threadIdx.x; v < (uint32_t)G * tvox; v += kTileBlock) s_keys[v] = kEmptyKey;
     while (job < nne) {
         const uint32_t at = job < nheavy ? job : H.gtiles - 1u - (job - nheavy);
@@ -653,7 +655,7 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
         }
         // next tile from this workgroup's queue
         if (threadIdx.x == 0)
-            s_job = gridDim.x + queue + kQueues * atomicAdd(&B.ctl->work[queue * kQueueStride], 1u);
+            s_job = gridDim.x + queue + nq * atomicAdd(&B.ctl->work[queue * kQueueStride], 1u);
         __syncthreads();
         job = uniform(s_job);
     }

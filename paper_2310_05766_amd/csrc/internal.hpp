@@ -130,7 +130,7 @@ struct InterpScan {
     int32_t w_max;
     unsigned long long *keys;      // [nx*ny*nz] per-scan keys, all EMPTY between scans
     uint8_t *touched;              // [ceil(nx*ny*nz / 64)] runs of 64 slots with a key, all 0 between scans
-    unsigned long long *counters;  // valid points, visits, voxels updated (added to)
+    unsigned long long *counters;  // valid points, visits, voxels updated, 64-bit atomics issued (added to)
 };
 hipError_t launch_interp(const InterpScan &P, int64_t nvox, hipStream_t stream);
 

@@ -99,7 +99,7 @@ __device__ __forceinline__ void block_add(uint64_t v, unsigned long long *dst)
 __global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
 {
     const int64_t i = (int64_t)blockIdx.x * kInterpBlock + threadIdx.x;
-    uint64_t valid = 0, visits = 0;
+    uint64_t valid = 0, visits = 0, atomics = 0;
     int32_t q[3];
     Ray R;
     if (i < P.n && quantise(P.xyz[3 * i], P.xyz[3 * i + 1], P.xyz[3 * i + 2], P.rp, q) && make_ray(q, P.rp, R)) {
@@ -163,25 +163,30 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
                     atomicMin(&P.keys[slot], key);
                     P.touched[slot >> 6] = 1;
                     ++visits;
+                    ++atomics;
                 }
             } while (walk_next(FW));
         } while (walk_next(W));
     }
     block_add(valid, &P.counters[0]);
     block_add(visits, &P.counters[1]);
+    block_add(atomics, &P.counters[3]);
 }
 
 // One candidate: the atomic only when it would lower the key read, the
 // run's mark only by a thread that read EMPTY (the first atomic on a slot in
 // a scan comes from such a thread: no key can be read before one is written).
-__device__ __forceinline__ void offer_key(const InterpScan &P, int64_t sl, uint64_t key)
+// Returns 1 when it issued the atomic.
+__device__ __forceinline__ uint32_t offer_key(const InterpScan &P, int64_t sl, uint64_t key)
 {
     unsigned long long *k = &P.keys[sl];
     const unsigned long long seen = *k;
     if (seen > key) {
         atomicMin(k, (unsigned long long)key);
         if (seen == kEmptyKey) P.touched[sl >> 6] = 1;
+        return 1;
     }
+    return 0;
 }
 
 // Free-space walks of neighbouring points (consecutive indices: neighbouring
@@ -202,15 +207,17 @@ __device__ __forceinline__ void offer_key(const InterpScan &P, int64_t sl, uint6
 // meet, over the whole launch instead of its first waves. Chunk 0 also walks
 // the band. Four waves per SIMD: held to five, the walk state spills.
 __global__ __launch_bounds__(kInterpBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_carve_scan(InterpScan P,
-                                                                                                      int64_t npad)
+                                                                                                      int64_t nch,
+                                                                                                      int64_t block0)
 {
-    const int64_t t = (int64_t)blockIdx.x * kInterpBlock + threadIdx.x;
-    const int64_t nch = (int64_t)gridDim.x * kInterpBlock / npad;
+    // block0: this launch's first block of the whole grid (the grid may be
+    // split over several launches)
+    const int64_t t = (block0 + (int64_t)blockIdx.x) * kInterpBlock + threadIdx.x;
     const int64_t w = t >> 6;
     const int64_t i = (w / nch) * 64 + (t & 63);
     const int32_t chunk = (int32_t)(w % nch);
     const int lane = (int)(threadIdx.x & 63u);
-    uint64_t valid = 0, visits = 0;
+    uint64_t valid = 0, visits = 0, atomics = 0;
     int32_t q[3];
     Ray R;
     int32_t lo[3], hi[3];
@@ -260,7 +267,7 @@ __global__ __launch_bounds__(kInterpBlock) __attribute__((amdgpu_waves_per_eu(4,
         const int64_t left_sl = __shfl_up(sl, 1);
         const uint64_t left_key = __shfl_up(key, 1);
         if (act) {
-            if (!(lane > 0 && left_sl == sl && left_key <= key)) offer_key(P, sl, key);
+            if (!(lane > 0 && left_sl == sl && left_key <= key)) atomics += offer_key(P, sl, key);
             ++visits;
             act = free_walk_next(F);
         }
@@ -273,13 +280,14 @@ __global__ __launch_bounds__(kInterpBlock) __attribute__((amdgpu_waves_per_eu(4,
             bool inside = true;
             for (int a = 0; a < 3; ++a) inside = inside && W.g[a] >= lo[a] && W.g[a] < hi[a];
             if (inside) {
-                offer_key(P, window_slot(P, W.g), pack_key(voxel_sdf(W.n, R, P.rp.tau), (uint32_t)i));
+                atomics += offer_key(P, window_slot(P, W.g), pack_key(voxel_sdf(W.n, R, P.rp.tau), (uint32_t)i));
                 ++visits;
             }
         } while (walk_next(W));
     }
     block_add(valid, &P.counters[0]);
     block_add(visits, &P.counters[1]);
+    block_add(atomics, &P.counters[3]);
 }
 
 // One wave per group of 64 runs of 64 slots: the wave reads the group's 64
@@ -335,9 +343,13 @@ hipError_t launch_interp(const InterpScan &P, int64_t nvox, hipStream_t stream)
             int32_t dmax = P.dims[0] > P.dims[1] ? P.dims[0] : P.dims[1];
             dmax = dmax > P.dims[2] ? dmax : P.dims[2];
             const int64_t nchunk = ((int64_t)dmax + (1 << kCarveChunkLog2) - 1) / (1 << kCarveChunkLog2) + 1;
-            const int64_t npad = blocks * kInterpBlock;
-            hipLaunchKernelGGL(k_carve_scan, dim3((uint32_t)(blocks * nchunk)), dim3(kInterpBlock), 0, stream, P,
-                               npad);
+            // blocks * nchunk blocks in launches of at most 2^23 blocks
+            // (2^31 work-items), so that no grid exceeds a launch's limits
+            const int64_t total = blocks * nchunk, per = (int64_t)1 << 23;
+            for (int64_t b0 = 0; b0 < total; b0 += per) {
+                const int64_t nb = total - b0 < per ? total - b0 : per;
+                hipLaunchKernelGGL(k_carve_scan, dim3((uint32_t)nb), dim3(kInterpBlock), 0, stream, P, nchunk, b0);
+            }
         } else
             hipLaunchKernelGGL(k_interp_scan, dim3((uint32_t)blocks), dim3(kInterpBlock), 0, stream, P);
     }

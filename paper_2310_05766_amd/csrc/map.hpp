@@ -1,0 +1,81 @@
+// The map object behind the C ABI's opaque tsdf_map, shared by the
+// library's translation units (runtime.hip holds its calls).
+#pragma once
+
+#include <atomic>
+#include <memory>
+
+#include "engine.hpp"
+
+struct tsdf_map {
+    tsdf_map_desc d;
+    int64_t nvox = 0;
+    double scale = 0.0;
+    int16_t *sdf = nullptr, *w = nullptr;
+    bool own_arrays = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    int32_t lt[3] = {0, 0, 0};  // integration tiling; {0, 0, 0}: chosen per call
+    int32_t tile_grid = 0;      // 0: as many workgroups as fit the device
+    std::unique_ptr<tsdf::Engine> engine;  // single-scan integration on the map's stream
+    // vertical interpolation between scan lines, or free-space carving (their
+    // own path through a key volume over the window, interp.hip)
+    int64_t interp_dq = 0;                     // delta_z of Eq. (3), 1/2^20 units; 0: off
+    bool carve = false;                        // rays longer than tau walked from the sensor
+    unsigned long long *interp_keys = nullptr;  // [nvox], EMPTY between scans
+    uint8_t *interp_touched = nullptr;          // [ceil(nvox / 64)], 0 between scans
+    unsigned long long *interp_ctr = nullptr;   // device counters (3)
+    unsigned long long *interp_ctr_host = nullptr;
+    float *interp_pts = nullptr;                // device copy of host points
+    int64_t interp_pts_cap = 0;                 // points
+    // shift / readback staging
+    int16_t *stage_dev = nullptr;  // [2][stage_cap]
+    int16_t *stage_host = nullptr;
+    int64_t stage_cap = 0;  // voxels per array
+    tsdf::BoxXfer *boxes_dev = nullptr;
+    tsdf::BoxXfer *boxes_host = nullptr;
+    int32_t boxes_cap = 0;
+    // per-kernel event timing (pack, unpack)
+    bool prof_on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[TSDF_KERNEL_COUNT];
+    std::vector<hipEvent_t> ev_pool;
+    // state
+    bool poisoned = false;
+    std::atomic<int> busy{0};
+    std::unordered_map<tsdf::ChunkKey, tsdf::Chunk, tsdf::ChunkKeyHash> store;
+};
+
+namespace tsdf {
+
+// One host thread per map: a call holds the map's busy flag while it runs.
+struct Guard {
+    tsdf_map *m;
+    bool ok;
+    explicit Guard(tsdf_map *mm) : m(mm), ok(false)
+    {
+        int expected = 0;
+        ok = m->busy.compare_exchange_strong(expected, 1);
+    }
+    ~Guard()
+    {
+        if (ok) m->busy.store(0);
+    }
+};
+
+
+// Tiles of 2^lt voxels: every lt in [2, 6], the z edge at least 8 (merge
+// runs), 2^9..2^12 voxels per tile (12 bytes of LDS per voxel).
+// Tilings used while a map has none set: scan-by-scan calls do best with
+// few, large tiles (per-tile fixed costs dominate one scan's work); batches
+// with many scans per tile do best with 8^3 tiles.
+inline constexpr int32_t kPlainTiling[3] = {4, 4, 3};
+inline constexpr int32_t kBatchTiling[3] = {3, 3, 3};
+
+inline const int32_t *tiling_for(const tsdf_map *m, bool batch)
+{
+    if (m->lt[0] != 0) return m->lt;
+    return batch ? kBatchTiling : kPlainTiling;
+}
+
+}  // namespace tsdf

@@ -307,6 +307,19 @@ __device__ __forceinline__ double crossings_upto(double T0, double dT, int typ, 
     return c;
 }
 
+// Crossing counts of the three axes (each below 2^7: a band segment spans at
+// most (3 tau + 2) / 1024 + 1 < 98 voxel faces per axis) in two packings:
+// 8 bits per axis (the entry record) and 7 bits per axis (21 bits, beside a
+// 10-bit slot in one 32-bit word).
+__device__ __forceinline__ uint32_t counts_8to7(uint32_t c)
+{
+    return (c & 0x7fu) | ((c >> 8) & 0x7fu) << 7 | ((c >> 16) & 0x7fu) << 14;
+}
+__device__ __forceinline__ uint32_t counts_7to8(uint32_t c)
+{
+    return (c & 0x7fu) | ((c >> 7) & 0x7fu) << 8 | ((c >> 14) & 0x7fu) << 16;
+}
+
 // Apply c[a] crossings on each axis to a freshly initialised voxel walk (the
 // state right after the event whose crossing counts they are).
 __device__ __forceinline__ void walk_advance(Walk &W, const int32_t c[3])

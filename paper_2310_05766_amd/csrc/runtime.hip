@@ -10,64 +10,11 @@
 #include <memory>
 #include <new>
 
-#include "engine.hpp"
+#include "map.hpp"
 
 using namespace tsdf;
 
-struct tsdf_map {
-    tsdf_map_desc d;
-    int64_t nvox = 0;
-    double scale = 0.0;
-    int16_t *sdf = nullptr, *w = nullptr;
-    bool own_arrays = false;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int device = 0;
-    int32_t lt[3] = {0, 0, 0};  // integration tiling; {0, 0, 0}: chosen per call
-    int32_t tile_grid = 0;      // 0: as many workgroups as fit the device
-    std::unique_ptr<Engine> engine;  // single-scan integration on the map's stream
-    // vertical interpolation between scan lines, or free-space carving (their
-    // own path through a key volume over the window, interp.hip)
-    int64_t interp_dq = 0;                     // delta_z of Eq. (3), 1/2^20 units; 0: off
-    bool carve = false;                        // rays longer than tau walked from the sensor
-    unsigned long long *interp_keys = nullptr;  // [nvox], EMPTY between scans
-    uint8_t *interp_touched = nullptr;          // [ceil(nvox / 64)], 0 between scans
-    unsigned long long *interp_ctr = nullptr;   // device counters (3)
-    unsigned long long *interp_ctr_host = nullptr;
-    float *interp_pts = nullptr;                // device copy of host points
-    int64_t interp_pts_cap = 0;                 // points
-    // shift / readback staging
-    int16_t *stage_dev = nullptr;  // [2][stage_cap]
-    int16_t *stage_host = nullptr;
-    int64_t stage_cap = 0;  // voxels per array
-    BoxXfer *boxes_dev = nullptr;
-    BoxXfer *boxes_host = nullptr;
-    int32_t boxes_cap = 0;
-    // per-kernel event timing (pack, unpack)
-    bool prof_on = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[TSDF_KERNEL_COUNT];
-    std::vector<hipEvent_t> ev_pool;
-    // state
-    bool poisoned = false;
-    std::atomic<int> busy{0};
-    std::unordered_map<ChunkKey, Chunk, ChunkKeyHash> store;
-};
-
 namespace {
-
-struct Guard {
-    tsdf_map *m;
-    bool ok;
-    explicit Guard(tsdf_map *mm) : m(mm), ok(false)
-    {
-        int expected = 0;
-        ok = m->busy.compare_exchange_strong(expected, 1);
-    }
-    ~Guard()
-    {
-        if (ok) m->busy.store(0);
-    }
-};
 
 tsdf_status fail_device(tsdf_map *m)
 {
@@ -148,20 +95,6 @@ bool desc_ok(const tsdf_map_desc *d)
 }
 
 int64_t nvox_of(const tsdf_map_desc *d) { return (int64_t)d->dims[0] * d->dims[1] * d->dims[2]; }
-
-// Tiles of 2^lt voxels: every lt in [2, 6], the z edge at least 8 (merge
-// runs), 2^9..2^12 voxels per tile (12 bytes of LDS per voxel).
-// Tilings used while a map has none set: scan-by-scan calls do best with
-// few, large tiles (per-tile fixed costs dominate one scan's work); batches
-// with many scans per tile do best with 8^3 tiles.
-constexpr int32_t kPlainTiling[3] = {4, 4, 3};
-constexpr int32_t kBatchTiling[3] = {3, 3, 3};
-
-const int32_t *tiling_for(const tsdf_map *m, bool batch)
-{
-    if (m->lt[0] != 0) return m->lt;
-    return batch ? kBatchTiling : kPlainTiling;
-}
 
 bool tiling_ok(const int32_t lt[3])
 {
@@ -582,6 +515,8 @@ static tsdf_status integrate_interp(tsdf_map *m, const float *xyz, int64_t n, bo
         HIPCHK(m, hipStreamSynchronize(m->stream));
         P.xyz = m->interp_pts;
     }
+    // the first three counters are per scan; the atomics counter (fourth)
+    // adds up until tsdf_map_key_atomics reads it
     HIPCHK(m, launch_fill_u32((uint32_t *)m->interp_ctr, 6, 0u, m->stream));
     HIPCHK(m, launch_interp(P, m->nvox, m->stream));
     if (stats) {
@@ -623,6 +558,7 @@ static tsdf_status ensure_key_volume(tsdf_map *m)
     }
     HIPCHK(m, launch_fill_u32((uint32_t *)m->interp_keys, m->nvox * 2, 0xffffffffu, m->stream));
     HIPCHK(m, launch_fill_u32((uint32_t *)m->interp_touched, (int64_t)(touched_bytes / 4), 0u, m->stream));
+    HIPCHK(m, launch_fill_u32((uint32_t *)m->interp_ctr, 8, 0u, m->stream));
     return TSDF_OK;
 }
 
@@ -900,6 +836,22 @@ tsdf_status tsdf_map_set_carving(tsdf_map *m, int32_t on)
         if (st != TSDF_OK) return st;
     }
     m->carve = on != 0;
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_map_key_atomics(tsdf_map *m, int64_t *issued)
+{
+    if (!m || !issued) return TSDF_EINVAL;
+    Guard g(m);
+    if (!g.ok) return TSDF_EBUSY;
+    if (m->poisoned) return TSDF_EDEVICE;
+    *issued = 0;
+    if (!m->interp_ctr) return TSDF_OK;  // no key volume yet: nothing issued
+    HIPCHK(m, hipMemcpyAsync(m->interp_ctr_host + 3, m->interp_ctr + 3, sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(m, hipStreamSynchronize(m->stream));
+    *issued = (int64_t)m->interp_ctr_host[3];
+    HIPCHK(m, launch_fill_u32((uint32_t *)(m->interp_ctr + 3), 2, 0u, m->stream));
     return TSDF_OK;
 }
 

@@ -43,6 +43,28 @@ def _points_arg(xyz):
     return xyz.data_ptr(), xyz.shape[0], _abi.TSDF_PTR_DEVICE, xyz
 
 
+_ext_streams = {}
+
+
+def _use_on_stream(tensors, handle):
+    """Order device points for the library's stream: that stream waits for
+    torch's current stream (where the tensors were written), and torch's
+    caching allocator is told that the stream uses them, so that a tensor
+    freed by the caller is not reused before the library has read it. No-op
+    when the library's stream is torch's current stream."""
+    import torch
+
+    cur = torch.cuda.current_stream()
+    if handle is None or cur.cuda_stream == handle:
+        return
+    ext = _ext_streams.get(handle)
+    if ext is None:
+        ext = _ext_streams[handle] = torch.cuda.ExternalStream(handle)
+    ext.wait_stream(cur)
+    for t in tensors:
+        t.record_stream(ext)
+
+
 _live = weakref.WeakSet()
 
 
@@ -78,6 +100,7 @@ class TsdfMap:
             check(L.tsdf_map_create_in(C.byref(self.desc), sdf.data_ptr(), w.data_ptr(), scratch.data_ptr(),
                                        scratch.numel() * scratch.element_size(), sh, C.byref(self._h)),
                   "tsdf_map_create_in")
+        self._stream = self.device_arrays()[2]  # the map's HIP stream
         _live.add(self)
 
     @staticmethod
@@ -112,8 +135,12 @@ class TsdfMap:
         self.close()
 
     def integrate(self, xyz, pose, stats: bool = False):
-        """tsdf_integrate_scan. With stats=True waits and returns the counts."""
+        """tsdf_integrate_scan. With stats=True waits and returns the counts.
+        Device points are read on the map's stream after torch's current
+        stream has written them; the tensor may be freed at once."""
         ptr, n, kind, _keep = _points_arg(xyz)
+        if kind == _abi.TSDF_PTR_DEVICE:
+            _use_on_stream([xyz], self._stream)
         _M, Mp = _pose_arg(pose)
         st = _abi.ScanStats() if stats else None
         check(_abi.lib().tsdf_integrate_scan(self._h, ptr, n, kind, Mp, C.byref(st) if stats else None),
@@ -173,6 +200,8 @@ class TsdfMap:
         """Point-to-TSDF registration of a scan against this map: (pose,
         info) with info = points_used, cost, last_step, steps."""
         ptr, n, kind, keep = _points_arg(xyz)
+        if kind == _abi.TSDF_PTR_DEVICE:
+            _use_on_stream([xyz], self._stream)
         M, Mp = _pose_arg(init_pose)
         out = np.zeros(16)
         info = _abi.RegisterInfo()
@@ -185,6 +214,8 @@ class TsdfMap:
 
     def register_sums(self, xyz, pose) -> np.ndarray:
         ptr, n, kind, keep = _points_arg(xyz)
+        if kind == _abi.TSDF_PTR_DEVICE:
+            _use_on_stream([xyz], self._stream)
         M, Mp = _pose_arg(pose)
         out = np.zeros(29)
         check(_abi.lib().tsdf_register_sums(self._h, C.cast(ptr, C.POINTER(C.c_float)), n, kind, Mp,
@@ -226,6 +257,12 @@ class TsdfMap:
         check(_abi.lib().tsdf_map_get_carving(self._h, C.byref(v)), "tsdf_map_get_carving")
         return bool(v.value)
 
+    def key_atomics(self) -> int:
+        """64-bit atomics the key-volume paths issued since the last call."""
+        v = C.c_int64()
+        check(_abi.lib().tsdf_map_key_atomics(self._h, C.byref(v)), "tsdf_map_key_atomics")
+        return int(v.value)
+
     def set_tiling(self, log2_tile, workgroups: int = 0):
         """Candidate-buffer tiling (2^log2_tile voxels per axis); results do not depend on it."""
         lt = (C.c_int32 * 3)(*[int(v) for v in log2_tile])
@@ -256,7 +293,9 @@ assert _SCAN_DTYPE.itemsize == C.sizeof(_abi.ScanDesc)
 
 def integrate_batch(items, stream=None, stats: bool = False):
     """tsdf_integrate_batch over [(TsdfMap, xyz, pose), ...]; scans sharing a
-    map are applied in list order. All points must be of one kind."""
+    map are applied in list order. All points must be of one kind. Device
+    points are read on the batch's stream (stream, else the first map's)
+    after torch's current stream has written them."""
     n = len(items)
     arr = np.zeros(max(n, 1), dtype=_SCAN_DTYPE)
     keep = []
@@ -272,6 +311,9 @@ def integrate_batch(items, stream=None, stats: bool = False):
     if len(kinds) > 1:
         raise ValueError("a batch takes host points or device points, not both")
     kind = kinds.pop() if kinds else _abi.TSDF_PTR_HOST
+    if kind == _abi.TSDF_PTR_DEVICE and n > 0:
+        run_on = _stream_handle(stream) if stream is not None else items[0][0]._stream
+        _use_on_stream([x for _, x, _ in items], run_on)
     st = (_abi.ScanStats * max(n, 1))() if stats else None
     check(_abi.lib().tsdf_integrate_batch(arr.ctypes.data_as(C.POINTER(_abi.ScanDesc)), n, kind,
                                           _stream_handle(stream), st), "tsdf_integrate_batch")
@@ -305,16 +347,3 @@ def batch_profile_read(stream, stage: str):
     check(_abi.lib().tsdf_batch_profile_read(_stream_handle(stream), BATCH_STAGES[stage], C.byref(ms), C.byref(n)),
           "tsdf_batch_profile_read")
     return float(ms.value), int(n.value)
-
-
-def atomic_probe(keys, waves: int = 2048, per_lane: int = 128, pattern: int = 0, stream=None) -> float:
-    """Milliseconds for waves * 64 * per_lane scattered 64-bit atomicMins on
-    the int64 device tensor keys (overwritten); pattern 1 keeps them in its
-    first 4 MiB. A measurement aid for the key-volume paths."""
-    import torch
-    if not (isinstance(keys, torch.Tensor) and keys.is_cuda and keys.dtype == torch.int64 and keys.is_contiguous()):
-        raise TypeError("keys must be a contiguous int64 CUDA tensor")
-    ms = C.c_float()
-    check(_abi.lib().tsdf_atomic_probe(C.c_void_p(keys.data_ptr()), keys.numel(), int(waves), int(per_lane),
-                                       int(pattern), _stream_handle(stream), C.byref(ms)), "tsdf_atomic_probe")
-    return float(ms.value)

@@ -8,6 +8,7 @@
 // exactly the voxels of the plain voxel walk that lie in that box, and every
 // such voxel must be reached from some tile. The test driver defines RAY_HPP
 // (a copy of ray.hpp whose one inline-asm minimum is replaced by a compare).
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -38,6 +39,7 @@ int main(int argc, char **argv)
     std::mt19937_64 rng(argc > 1 ? strtoull(argv[1], nullptr, 10) : 11);
     const int iters = argc > 2 ? atoi(argv[2]) : 20000;
     long bad = 0, tiles = 0, visits = 0, rays = 0;
+    int32_t max_count = 0;
     for (int it = 0; it < iters; ++it) {
         RayParams P{};
         const int64_t lim = 1ll << std::uniform_int_distribution<int>(0, 24)(rng);
@@ -86,6 +88,21 @@ int main(int argc, char **argv)
                 if (t_in >= 0.0)
                     for (int a = 0; a < 3; ++a)
                         c[a] = (int32_t)crossings_upto(Wv.T[a], Wv.dT[a], Wv.step[a] > 0 ? 0 : 1, t_in, typ_in);
+                // through the binning's packings: 8 bits per axis, then 7
+                // bits per axis beside a 10-bit slot, and back
+                {
+                    uint32_t c8 = 0;
+                    for (int a = 0; a < 3; ++a) {
+                        if (c[a] < 0 || c[a] > 127) ++bad;  // outside the packed range
+                        c8 |= (uint32_t)c[a] << (8 * a);
+                    }
+                    const uint32_t word = 1023u | counts_8to7(c8) << 10;
+                    const uint32_t back = counts_7to8(word >> 10);
+                    for (int a = 0; a < 3; ++a) {
+                        if ((int32_t)((back >> (8 * a)) & 0xffu) != c[a]) ++bad;
+                        max_count = std::max(max_count, c[a]);
+                    }
+                }
                 // tile side
                 int32_t blo[3], bhi[3];
                 for (int a = 0; a < 3; ++a) {
@@ -138,6 +155,7 @@ int main(int argc, char **argv)
             }
         }
     }
-    printf("rays %ld tiles %ld visits %ld mismatches %ld\n", rays, tiles, visits, bad);
+    printf("rays %ld tiles %ld visits %ld largest crossing count %d mismatches %ld\n", rays, tiles, visits, max_count,
+           bad);
     return bad != 0 || visits == 0;
 }

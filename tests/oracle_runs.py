@@ -68,3 +68,45 @@ def window_digest(sdf: np.ndarray, w: np.ndarray) -> str:
     h.update(np.ascontiguousarray(sdf).tobytes())
     h.update(np.ascontiguousarray(w).tobytes())
     return h.hexdigest()
+
+
+def session_scans(args):
+    """All scans of one config-5 session as stacked arrays (a worker job; no
+    oracle call): (sid, xyz [n, 16384, 3] float32, poses [n, 4, 4])."""
+    sid, n_sessions, duration = args
+    sess = synth.config5(n_sessions=n_sessions, duration_s=duration)[sid]
+    n = len(sess.arrivals)
+    xyz = np.empty((n, 16 * 1024, 3), np.float32)
+    poses = np.empty((n, 4, 4), np.float64)
+    for k in range(n):
+        sc = sess.scan(k)
+        xyz[k] = sc.xyz
+        poses[k] = sc.pose
+    return sid, xyz, poses
+
+
+def all_session_scans(n_sessions: int, duration: float):
+    """Every scan of every config-5 session, generated in worker processes."""
+    ctx = mp.get_context("spawn")
+    workers = max(1, min(15, len(os.sched_getaffinity(0)) - 1))
+    with ctx.Pool(workers) as pool:
+        out = pool.map(session_scans, [(s, n_sessions, duration) for s in range(n_sessions)])
+    return {sid: (x, p) for sid, x, p in out}
+
+
+def load_digests():
+    """The oracle's digests of the full-size workloads (written by
+    tests/golden/make_oracle_digests.py, which calls only the oracle)."""
+    import json
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_digests.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def input_digest(scans) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for xyz, pose in scans:
+        h.update(np.ascontiguousarray(xyz, dtype=np.float32).tobytes())
+        h.update(np.ascontiguousarray(pose, dtype=np.float64).tobytes())
+    return h.hexdigest()

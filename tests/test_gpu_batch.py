@@ -121,6 +121,28 @@ def test_every_tiling_gives_the_same_map(lt):
     om.close()
 
 
+@pytest.mark.parametrize("workgroups", [1, 3, 7, 8, 9])
+def test_few_tile_workgroups_drain_every_queue(workgroups):
+    """Grids smaller than the number of work queues (one per XCD): every busy
+    tile is still processed, over two batches in a row (the second starts
+    from the per-tile counts the first left), bit-exact with the oracle."""
+    from paper_2310_05766_amd.tsdf import integrate_batch
+    w = synth.config1()
+    spec, sc = w.maps[0], w.scans[0]
+    om = oracle.OracleMap.from_spec(spec)
+    gm = gpu_map(spec.dims, spec.origin, spec.voxel_size, spec.tau_u, spec.w_max)
+    gm.set_tiling((3, 3, 3), workgroups)
+    assert gm.get_tiling() == ((3, 3, 3), workgroups)
+    for b in range(2):
+        poses = [synth.fuzz_pose((workgroups, b, k), 0.4) for k in range(3)]
+        st = integrate_batch([(gm, sc.xyz, p) for p in poses], stats=True)
+        assert st == [om.integrate(sc.xyz, p) for p in poses], (workgroups, b)
+        assert gm.integrate(sc.xyz, sc.pose, stats=True) == om.integrate(sc.xyz, sc.pose)
+    assert same(gm, om, spec.dims)
+    gm.close()
+    om.close()
+
+
 def test_invalid_tilings_rejected():
     from paper_2310_05766_amd import TsdfError
     gm = gpu_map((32, 32, 32), (-16, -16, -16), 0.05, 3072, 64)

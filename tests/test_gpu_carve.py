@@ -191,12 +191,12 @@ def test_carving_arguments():
 
 
 def test_atomic_probe():
-    """The measurement aid behind the key-volume roofline: it applies
-    atomicMins inside the buffer (pattern 1 only to its first 2^19 keys) and
-    checks its arguments."""
+    """The benchmark's measurement aid behind the key-volume roofline (its
+    own library, not the TSDF library): it applies atomicMins inside the
+    buffer (pattern 1 only to its first 2^19 keys) and checks its
+    arguments."""
     import torch
-    from paper_2310_05766_amd import TsdfError
-    from paper_2310_05766_amd.tsdf import atomic_probe
+    from paper_2310_05766_amd.probe import atomic_probe
     keys = torch.full((1 << 20,), -1, dtype=torch.int64, device="cuda")
     assert atomic_probe(keys, 64, 8, 1) > 0
     torch.cuda.synchronize()
@@ -205,7 +205,7 @@ def test_atomic_probe():
     torch.cuda.synchronize()
     assert int((keys[1 << 19:] != -1).sum()) > 0
     for args in [(keys[:1000], 64, 8, 1), (keys, 63, 8, 0), (keys, 64, 0, 0), (keys, 64, 8, 2)]:
-        with pytest.raises(TsdfError):
+        with pytest.raises(ValueError):
             atomic_probe(*args)
 
 

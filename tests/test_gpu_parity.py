@@ -350,3 +350,31 @@ def test_extreme_coordinates():
         assert_same_window(gm, om, dims)
         gm.close()
         om.close()
+
+
+def test_fused_transform_chain_crafted_rounding():
+    """The case where the fused transform chain and separately rounded
+    products give different fixed-point coordinates (x = 1 + 2^-23 under
+    M[0][0] = 1 + 2^-30, translation cancelling to 2^-11: q_x = 1 fused,
+    0 unfused): the GPU map equals the oracle's, and differs from the map of
+    the same point moved by one unit."""
+    x = 1.0 + 2.0 ** -23
+    M = np.eye(4)
+    M[0, 0] = 1.0 + 2.0 ** -30
+    M[0, 3] = -(1.0 + 2.0 ** -23 + 2.0 ** -30) + 2.0 ** -11
+    pts = np.array([[x, 0.0, 0.0]], dtype=np.float32)
+    assert oracle.quantise_point(pts[0], M, 1024.0)[0] == 1
+    dims, origin, tau = (16, 8, 8), (-8, -4, -4), 1536
+    om = oracle.OracleMap(dims, origin, 1.0, tau, 64)
+    gm = gpu_map(dims, origin, 1.0, tau, 64)
+    assert gm.integrate(pts, M, stats=True) == om.integrate(pts, M)
+    assert_same_window(gm, om, dims)
+    # the unfused rounding would put q_x at 0: a different map
+    off = oracle.OracleMap(dims, origin, 1.0, tau, 64)
+    M2 = M.copy()
+    M2[0, 3] -= 2.0 ** -10
+    off.integrate(pts, M2)
+    o = window_box(origin, dims)
+    assert not np.array_equal(off.readback(*o)[0], om.readback(*o)[0])
+    for m in (gm, om, off):
+        m.close()
