@@ -44,14 +44,21 @@ def _points_arg(xyz):
 
 
 _ext_streams = {}
+_held_by_stream = {}  # stream handle -> device tensors a caller-given raw stream may still read
+_HOLD_MAX = 64
 
 
-def _use_on_stream(tensors, handle):
-    """Order device points for the library's stream: that stream waits for
-    torch's current stream (where the tensors were written), and torch's
-    caching allocator is told that the stream uses them, so that a tensor
-    freed by the caller is not reused before the library has read it. No-op
-    when the library's stream is torch's current stream."""
+def _torch_stream(stream):
+    """The torch stream object behind a stream argument, if it is one."""
+    if stream is None or isinstance(stream, int):
+        return None
+    return stream
+
+
+def _order_after_torch(handle):
+    """The library's stream (handle) waits for torch's current stream, where
+    the device points were written: a torch event recorded on the current
+    stream, waited on by the library's stream. No-op for the same stream."""
     import torch
 
     cur = torch.cuda.current_stream()
@@ -60,9 +67,26 @@ def _use_on_stream(tensors, handle):
     ext = _ext_streams.get(handle)
     if ext is None:
         ext = _ext_streams[handle] = torch.cuda.ExternalStream(handle)
-    ext.wait_stream(cur)
-    for t in tensors:
-        t.record_stream(ext)
+    ev = torch.cuda.Event()
+    ev.record(cur)
+    ext.wait_event(ev)
+
+
+def _hold_raw(handle, tensors):
+    """Keep device points alive until a raw stream (one torch did not
+    create) has read them: held here and released after that stream is
+    synchronised (when the list grows long, or by _release_raw)."""
+    held = _held_by_stream.setdefault(handle, [])
+    if len(held) >= _HOLD_MAX:
+        ext = _ext_streams.get(handle)
+        if ext is not None:
+            ext.synchronize()
+        held.clear()
+    held.extend(tensors)
+
+
+def _release_raw(handle):
+    _held_by_stream.pop(handle, None)
 
 
 _live = weakref.WeakSet()
@@ -92,6 +116,10 @@ class TsdfMap:
         self._keep = None
         L = _abi.lib()
         sh = _stream_handle(stream)
+        # device points: a torch stream is told that the map reads them
+        # (record_stream); the library's own stream gets a keep-alive list
+        self._tstream = _torch_stream(stream)
+        self._held = []
         if arrays is None:
             check(L.tsdf_map_create(C.byref(self.desc), sh, C.byref(self._h)), "tsdf_map_create")
         else:
@@ -119,8 +147,22 @@ class TsdfMap:
 
     def close(self):
         if self._h:
-            check(_abi.lib().tsdf_map_destroy(self._h), "tsdf_map_destroy")
+            check(_abi.lib().tsdf_map_destroy(self._h), "tsdf_map_destroy")  # waits for the stream
             self._h = C.c_void_p()
+            self._held = []
+            _release_raw(self._stream)
+
+    def _use(self, tensors):
+        """Order device points for the map's stream and keep them alive until
+        it has read them."""
+        _order_after_torch(self._stream)
+        if self._tstream is not None:
+            for t in tensors:
+                t.record_stream(self._tstream)
+            return
+        if len(self._held) >= _HOLD_MAX:
+            self.synchronize()
+        self._held.extend(tensors)
 
     def __del__(self):
         try:
@@ -137,10 +179,11 @@ class TsdfMap:
     def integrate(self, xyz, pose, stats: bool = False):
         """tsdf_integrate_scan. With stats=True waits and returns the counts.
         Device points are read on the map's stream after torch's current
-        stream has written them; the tensor may be freed at once."""
+        stream has written them, and the map keeps them alive until its
+        stream has read them, so the caller may drop them at once."""
         ptr, n, kind, _keep = _points_arg(xyz)
         if kind == _abi.TSDF_PTR_DEVICE:
-            _use_on_stream([xyz], self._stream)
+            self._use([xyz])
         _M, Mp = _pose_arg(pose)
         st = _abi.ScanStats() if stats else None
         check(_abi.lib().tsdf_integrate_scan(self._h, ptr, n, kind, Mp, C.byref(st) if stats else None),
@@ -195,13 +238,14 @@ class TsdfMap:
 
     def synchronize(self):
         check(_abi.lib().tsdf_map_synchronize(self._h), "tsdf_map_synchronize")
+        self._held = []
 
     def register(self, xyz, init_pose, iterations: int = 10, damping: float = 1e-6):
         """Point-to-TSDF registration of a scan against this map: (pose,
         info) with info = points_used, cost, last_step, steps."""
         ptr, n, kind, keep = _points_arg(xyz)
         if kind == _abi.TSDF_PTR_DEVICE:
-            _use_on_stream([xyz], self._stream)
+            self._use([xyz])
         M, Mp = _pose_arg(init_pose)
         out = np.zeros(16)
         info = _abi.RegisterInfo()
@@ -215,7 +259,7 @@ class TsdfMap:
     def register_sums(self, xyz, pose) -> np.ndarray:
         ptr, n, kind, keep = _points_arg(xyz)
         if kind == _abi.TSDF_PTR_DEVICE:
-            _use_on_stream([xyz], self._stream)
+            self._use([xyz])
         M, Mp = _pose_arg(pose)
         out = np.zeros(29)
         check(_abi.lib().tsdf_register_sums(self._h, C.cast(ptr, C.POINTER(C.c_float)), n, kind, Mp,
@@ -312,8 +356,18 @@ def integrate_batch(items, stream=None, stats: bool = False):
         raise ValueError("a batch takes host points or device points, not both")
     kind = kinds.pop() if kinds else _abi.TSDF_PTR_HOST
     if kind == _abi.TSDF_PTR_DEVICE and n > 0:
-        run_on = _stream_handle(stream) if stream is not None else items[0][0]._stream
-        _use_on_stream([x for _, x, _ in items], run_on)
+        tensors = [x for _, x, _ in items]
+        if stream is None:
+            items[0][0]._use(tensors)  # the batch runs on the first scan's map's stream
+        else:
+            handle = _stream_handle(stream)
+            _order_after_torch(handle)
+            ts = _torch_stream(stream)
+            if ts is not None:
+                for t in tensors:
+                    t.record_stream(ts)
+            else:
+                _hold_raw(handle, tensors)
     st = (_abi.ScanStats * max(n, 1))() if stats else None
     check(_abi.lib().tsdf_integrate_batch(arr.ctypes.data_as(C.POINTER(_abi.ScanDesc)), n, kind,
                                           _stream_handle(stream), st), "tsdf_integrate_batch")
@@ -325,7 +379,8 @@ def integrate_batch(items, stream=None, stats: bool = False):
 
 def batch_release(stream):
     """Free the batch engine kept for a stream (call before destroying it)."""
-    check(_abi.lib().tsdf_batch_release(_stream_handle(stream)), "tsdf_batch_release")
+    check(_abi.lib().tsdf_batch_release(_stream_handle(stream)), "tsdf_batch_release")  # waits for it
+    _release_raw(_stream_handle(stream))
 
 
 def set_graph_launch(on: bool):
