@@ -119,6 +119,24 @@ typedef struct {
 tsdf_status tsdf_integrate_batch(const tsdf_scan_desc *scans, int32_t count, tsdf_ptr_kind kind,
                                  void *hip_stream, tsdf_scan_stats *stats /* count entries, nullable */);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): tsdf_integrate_scan of
+ * device points with no allocation and no graph. The batch engine's tables
+ * and entry records live in one fixed device array of 64 MiB per GPU, held
+ * by the library from its first use on that GPU until the process ends:
+ * enough for one scan of 131,072 points at tau = 5 voxels on a 512 x 512 x
+ * 256 window with the default tiling. Same arithmetic and result as
+ * tsdf_integrate_scan.
+ *  xyz_dev: device points (n_points x 3 float32), read on the map's stream.
+ *  stats:   NULL -> returns without waiting; otherwise waits and fills them.
+ * TSDF_ERANGE (map untouched) when the scan's tables would exceed the array;
+ * TSDF_EINVAL for a map with interpolation or carving on (they allocate a
+ * key volume) and for the arguments tsdf_integrate_scan rejects. Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (maps
+ * on different streams, or different host threads) race. */
+tsdf_status tsdf_integrate_scan_noalloc(tsdf_map *m, const float *xyz_dev, int64_t n_points,
+                                        const double world_T_sensor[16], tsdf_scan_stats *stats);
+
 /* A batch runs on hip_stream (NULL: the first scan's map's stream), ordered
  * after earlier work on every map it touches, and later work on those maps
  * is ordered after it. The library keeps a batch engine (device tables,
