@@ -195,43 +195,57 @@ def cpu_model() -> str:
 
 
 def shift_leg(torch, TsdfMap, synth, bw=None):
-    """One-chunk shifts of a 512 x 512 x 128 ring window at 5 cm and back.
-    Bytes over the host link: the evicted chunks (1 MiB each, sdf + w) that
-    hold an observed voxel go out, and entering chunks are loaded only when
-    the store holds them."""
+    """One-chunk shifts of a 512 x 512 x 128 ring window at 5 cm, back and
+    forth between two origins 64 voxels apart, with observed data in both
+    end slabs: config-1 room scans spread along y at the window's left end,
+    then (after one shift) at its right end. Every timed shift then sends the
+    16 chunks of the slab that leaves out to the host store (1 MiB each,
+    sdf + w) and loads the 16 of the slab that enters back from it."""
+    import numpy as np
+
     dims = (512, 512, 128)
-    m = TsdfMap(dims, (-256, -256, -64), 0.05, 3072, 64)
-    w1 = synth.config1()
-    sc = w1.scans[0]
-    for k in range(4):
-        m.integrate(sc.xyz, synth.fuzz_pose(700 + k, 2.0))
+    vs = 0.05
+    a_org = (-256, -256, -64)
+    b_org = (-192, -256, -64)
+    m = TsdfMap(dims, a_org, vs, 3072, 64)
+    sc = synth.config1().scans[0]
+    ys = [-11.0 + 22.0 * k / 7 for k in range(8)]
+
+    def fill(x):
+        for y in ys:
+            pose = np.eye(4)
+            pose[:3, 3] = [x, y, 0.0]
+            m.integrate(sc.xyz, pose)
+
+    fill(-11.2)  # the slab [-12.8, -9.6) m at the left end of the window at a_org
+    m.shift(b_org)
+    fill(14.4)   # the slab [12.8, 16.0) m at the right end of the window at b_org
     m.synchronize()
-    times, moved_out, moved_in, loaded = [], 0, 0, 0
-    o = m.origin
-    slab = 64 * dims[1] * dims[2] * 4  # one chunk layer: 16 chunks, sdf + w
+    times, moved_out, moved_in = [], 0, 0
+    chunk_bytes = 64 ** 3 * 4
+    loaded = None
     for k in range(6):
-        d = 64 if k % 2 == 0 else -64
-        new = (o[0] + d, o[1], o[2])
+        new = a_org if k % 2 == 0 else b_org
         c0, _ = m.store_info()
         t0 = time.perf_counter()
         m.shift(new)
         times.append(time.perf_counter() - t0)
         c1, _ = m.store_info()
-        o = new
-        # chunks in the store after = before + evicted (observed ones are
-        # kept) - loaded (popped); each shift brings back exactly what the
-        # previous one, its inverse, evicted
+        # every shift brings back what the shift before it evicted (its
+        # inverse); the store count moves by the evicted minus the loaded
+        if loaded is None:
+            loaded = 16  # the left slab, evicted by the set-up shift
         evicted = c1 - c0 + loaded
-        moved_out += evicted * (slab // 16)
-        moved_in += loaded * (slab // 16)
+        moved_out += evicted * chunk_bytes
+        moved_in += loaded * chunk_bytes
         loaded = evicted
     m.close()
     t = sum(times)
     out = {"window": list(dims), "shift_vox": 64, "shifts": len(times), "ms_per_shift": 1e3 * t / len(times),
            "bytes_out": moved_out, "bytes_in": moved_in, "host_link_GBps": (moved_out + moved_in) / t / 1e9}
     if bw:
-        # the time the same bytes take at the measured pinned rates, one
-        # direction after the other, over the measured shift time
+        # the same bytes at the measured pinned rates, one direction after
+        # the other (the shift overlaps the two directions, so this can pass 1)
         ideal = moved_out / (bw["pinned_d2h_GBps"] * 1e9) + moved_in / (bw["pinned_h2d_GBps"] * 1e9)
         out["frac_of_pinned"] = ideal / t
     return out

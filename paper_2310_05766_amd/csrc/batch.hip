@@ -54,29 +54,6 @@ __device__ __forceinline__ uint4 entry_ray(const Ray &R, uint32_t cpack)
     return make_uint4((uint32_t)R.r, o0 | o1 << 16, o2 | (cpack & 0xffffu) << 16, cpack >> 16);
 }
 
-// The ray of an entry record: as make_ray gives it, without its divisions.
-__device__ __forceinline__ void ray_of_entry(const uint4 &ra, const uint4 &rb, const int32_t o[3], int32_t tau,
-                                             Ray &R, int32_t c[3])
-{
-    const int32_t off[3] = {(int16_t)(rb.y & 0xffffu), (int16_t)(rb.y >> 16), (int16_t)(rb.z & 0xffffu)};
-    R.q[0] = (int32_t)ra.y;
-    R.q[1] = (int32_t)ra.z;
-    R.q[2] = (int32_t)ra.w;
-    R.r = (double)rb.x;
-    R.r2 = 2.0 * R.r;
-    R.inv_r2 = refined_rcp(R.r2);  // band_key's precondition
-    const bool near = R.r <= (double)tau;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        R.D[a] = (double)R.q[a] - (double)o[a];  // exact: both below 2^30 in magnitude
-        R.E[a] = R.q[a] + off[a];
-        R.S[a] = near ? o[a] : R.q[a] - off[a];
-    }
-    c[0] = (int32_t)((rb.z >> 16) & 0xffu);
-    c[1] = (int32_t)(rb.z >> 24);
-    c[2] = (int32_t)(rb.w & 0xffu);
-}
-
 template <bool kFill>
 __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
 {
@@ -559,20 +536,18 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                 const uint32_t i = ra.x;
                 const int32_t o[3] = {s_o[r][0], s_o[r][1], s_o[r][2]};
                 const int32_t tau = s_tau[r];
-                Ray R;
-                Walk W;
-                int32_t c[3];
-                ray_of_entry(ra, rb, o, tau, R, c);
-                walk_init(R, W);
+                const int32_t q[3] = {(int32_t)ra.y, (int32_t)ra.z, (int32_t)ra.w};
+                const int32_t off[3] = {(int16_t)(rb.y & 0xffffu), (int16_t)(rb.y >> 16), (int16_t)(rb.z & 0xffffu)};
+                const int32_t c[3] = {(int32_t)((rb.z >> 16) & 0xffu), (int32_t)(rb.z >> 24), (int32_t)(rb.w & 0xffu)};
                 // resume the walk right after the event that entered the
-                // tile; the box check only moves it further where the tile
-                // is clipped by the window's edge
-                walk_advance(W, c);
-                if (!walk_enter_box(W, blo, bhi)) continue;
-                // the voxels of the walk inside the box are one run
-                // (the walk carries the key's LDS address itself)
+                // tile, set down on its first voxel in the box; the voxels
+                // of the walk inside the box are one run (the walk carries
+                // the key's LDS address itself)
+                Ray R;
                 BoxWalk V;
-                box_walk_from(W, blo, bhi, shb, lds_address(s_keys + (size_t)r * tvox), V);
+                if (!box_walk_resume(q, off, rb.x, c, o, tau, blo, bhi, shb, lds_address(s_keys + (size_t)r * tvox), R,
+                                     V))
+                    continue;
                 const double taud = (double)tau;
                 const uint32_t ihi = i >> 16, ilo = i << 16;
                 uint32_t visits = 0;

@@ -180,8 +180,13 @@ struct ChunkKeyHash {
         return (size_t)h;
     }
 };
+// A chunk of the host store: kChunkVox sdf values then kChunkVox weights,
+// [x][y][z] z fastest, in pinned host memory (a buffer of the map's chunk
+// pool), so that a whole chunk crosses the host link in one copy.
 struct Chunk {
-    std::vector<int16_t> sdf, w;  // kChunkVox each, [x][y][z] z fastest
+    int16_t *buf = nullptr;
+    int16_t *sdf() const { return buf; }
+    int16_t *w() const { return buf + kChunkVox; }
 };
 
 // A box of voxels copied between the window and a dense staging buffer:
@@ -197,6 +202,14 @@ struct BoxXfer {
 hipError_t launch_pack_boxes(const BoxXfer *boxes_dev, int32_t nboxes, int64_t max_box_vox, int16_t *sdf,
                              int16_t *w, const int32_t dims[3], int16_t *stage_sdf, int16_t *stage_w, bool clear,
                              hipStream_t stream);
+// Whole chunks of a window whose dims are multiples of 64 (chunks_dev[j].lo:
+// the chunk's global origin), staged chunk by chunk in the store's layout
+// (stage + j * 2 * kChunkVox: sdf, then w). pack clears the window voxels and
+// sets flags[j] (zero beforehand) when chunk j holds a non-zero voxel.
+hipError_t launch_pack_chunks(const BoxXfer *chunks_dev, int32_t nchunks, int16_t *sdf, int16_t *w,
+                              const int32_t dims[3], int16_t *stage, uint32_t *flags, hipStream_t stream);
+hipError_t launch_unpack_chunks(const BoxXfer *chunks_dev, int32_t nchunks, int16_t *sdf, int16_t *w,
+                                const int32_t dims[3], const int16_t *stage, hipStream_t stream);
 hipError_t launch_unpack_boxes(const BoxXfer *boxes_dev, int32_t nboxes, int64_t max_box_vox, int16_t *sdf,
                                int16_t *w, const int32_t dims[3], const int16_t *stage_sdf,
                                const int16_t *stage_w, hipStream_t stream);

@@ -36,6 +36,18 @@ struct tsdf_map {
     tsdf::BoxXfer *boxes_dev = nullptr;
     tsdf::BoxXfer *boxes_host = nullptr;
     int32_t boxes_cap = 0;
+    // whole-chunk shifts: device staging of kShiftChunks chunks leaving and
+    // kShiftChunks entering, per-chunk non-zero flags (device, pinned host),
+    // chunk lists (pinned host, device), and a second stream for the copies
+    // into the window, so that both directions of the host link run together
+    int16_t *cstage_dev = nullptr;
+    uint32_t *cflags_dev = nullptr, *cflags_host = nullptr;
+    tsdf::BoxXfer *clist_host = nullptr, *clist_dev = nullptr;
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t copy_done = nullptr;
+    // the store's chunk buffers: pinned host slabs cut into 1 MiB chunks
+    std::vector<void *> pool_slabs;
+    std::vector<int16_t *> pool_free;
     // per-kernel event timing (pack, unpack)
     bool prof_on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[TSDF_KERNEL_COUNT];

@@ -63,6 +63,23 @@ __device__ __forceinline__ uint64_t isqrt_u64(uint64_t n)
 // afterwards, so its accuracy only decides how many correction steps run.
 __device__ __forceinline__ double approx_rcp(double d) { return __builtin_amdgcn_rcp(d); }
 
+// floor(sqrt(n)) for 0 < n < 3 * 2^62 (|D|^2 of a ray, so the root is below
+// 2^31.8): sqrt(n) estimated as n / sqrt(n) from the hardware reciprocal
+// square root (relative error far below 2^-20) with one Newton step, which
+// leaves a relative error near 2^-40, an absolute one far below 1; then one
+// exact correction each way in 64-bit integers ((r + 1)^2 < 2^64 here).
+__device__ __forceinline__ uint32_t isqrt_ray(uint64_t n)
+{
+    const double x = (double)n;
+    const double y = __builtin_amdgcn_rsq(x);
+    double s = x * y;
+    s = __fma_rn(0.5 * y, __fma_rn(-s, s, x), s);
+    uint32_t r = (uint32_t)fmin(fmax(s, 0.0), 4294967295.0);
+    r -= (uint64_t)r * r > n ? 1u : 0u;
+    r += (uint64_t)(r + 1u) * (r + 1u) <= n ? 1u : 0u;
+    return r;
+}
+
 // min(a, b) of two doubles that are never NaN, as one v_min_f64. fmin must
 // first quiet signalling NaNs, one v_max_f64 x, x per operand the compiler
 // cannot trace to an arithmetic result (loop-carried times, invariants), and
@@ -124,17 +141,16 @@ struct Ray {
 // S = q - off, or S = o when r <= tau. false for D = 0.
 __device__ __forceinline__ bool make_ray(const int32_t q[3], const RayParams &P, Ray &R)
 {
-    int64_t Di[3];
     uint64_t dd = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        Di[a] = (int64_t)q[a] - P.o[a];
-        dd += (uint64_t)(Di[a] * Di[a]);
+        const int32_t Di = q[a] - P.o[a];  // |q|, |o| < 2^30: fits
+        dd += (uint64_t)((int64_t)Di * Di);
         R.q[a] = q[a];
-        R.D[a] = (double)Di[a];
+        R.D[a] = (double)Di;
     }
     if (dd == 0) return false;
-    const uint64_t r = isqrt_u64(dd);
+    const uint32_t r = isqrt_ray(dd);
     R.r = (double)r;
     R.r2 = 2.0 * R.r;
     R.inv_r2 = approx_rcp(R.r2);
@@ -426,6 +442,61 @@ __device__ __forceinline__ void box_walk_from(const Walk &W, const int32_t lo[3]
     }
     V.lim = fmin(2.0 * W.lam, first_exit - 1.0);
     V.n = W.n;
+}
+
+// The box walk of one tile entry, straight from what the entry record holds:
+// the point q, the band offsets off = E - q, r = isqrt(|D|^2) and the voxel
+// crossings c[a] taken up to the event that entered the tile. Sets R (the
+// ray as make_ray gives it, with inv_r2 = refined_rcp(2r) as band_key
+// wants) and V, the state that walk_init, walk_advance(c), walk_enter_box
+// and box_walk_from give, with the resumed voxel walk formed directly
+// (crossing times and distance numerator at c crossings) instead of by a
+// walk from S; walk_enter_box only moves it where the tile is clipped by the
+// window's edge. false when no voxel of the walk lies in the box [lo, hi).
+// Integer ranges: |q|, |o| < 2^30, so D and the voxel offsets q - c fit
+// int32 (|q - c| stays within a voxel diagonal of the band, below 2^17);
+// the products below are exact in float64 (< 2^52).
+__device__ __forceinline__ bool box_walk_resume(const int32_t q[3], const int32_t off[3], uint32_t r,
+                                                const int32_t c[3], const int32_t o[3], int32_t tau,
+                                                const int32_t lo[3], const int32_t hi[3], const int32_t sh[3],
+                                                uint32_t base, Ray &R, BoxWalk &V)
+{
+    R.r = (double)r;
+    R.r2 = 2.0 * R.r;
+    R.inv_r2 = refined_rcp(R.r2);
+    const bool near = R.r <= (double)tau;
+    Walk W;
+    double f[3];
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        R.q[a] = q[a];
+        R.D[a] = (double)(q[a] - o[a]);
+        R.E[a] = q[a] + off[a];
+        R.S[a] = near ? o[a] : q[a] - off[a];
+        const int32_t L = R.E[a] - R.S[a];
+        W.step[a] = L > 0 ? 1 : (L < 0 ? -1 : 0);
+        f[a] = L != 0 ? (double)(L < 0 ? -L : L) : 1.0;
+        W.g[a] = (R.S[a] >> 10) + W.step[a] * c[a];  // arithmetic shift: floor division
+        inside = inside && W.g[a] >= lo[a] && W.g[a] < hi[a];
+    }
+    const double other[3] = {f[1] * f[2], f[0] * f[2], f[0] * f[1]};
+    W.lam = f[0] * f[1] * f[2];
+    double n = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        n += (double)(q[a] - 1024 * W.g[a] - 512) * R.D[a];
+        // distance from S to the first face ahead, then c[a] whole cells
+        const int32_t g0 = R.S[a] >> 10;
+        const int32_t ahead = W.step[a] > 0 ? 1024 * (g0 + 1) - R.S[a] : R.S[a] - 1024 * g0;
+        W.T[a] = W.step[a] != 0 ? (double)(ahead + 1024 * c[a]) * other[a] : INFINITY;
+        W.dT[a] = 1024.0 * other[a];
+        W.dn[a] = -1024.0 * R.D[a];
+    }
+    W.n = n;
+    if (!inside && !walk_enter_box(W, lo, hi)) return false;
+    box_walk_from(W, lo, hi, sh, base, V);
+    return true;
 }
 
 // Advance to the next voxel of the box; false when the walk leaves the box

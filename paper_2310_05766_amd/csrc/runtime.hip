@@ -154,6 +154,57 @@ tsdf_status ensure_stage(tsdf_map *m, int64_t vox, int32_t boxes)
     return TSDF_OK;
 }
 
+// Chunks of the host store come from pinned slabs of kPoolSlab chunks, so
+// that a whole chunk is one DMA copy to or from the device; a freed chunk
+// goes back to the pool (slabs are returned when the map is destroyed).
+constexpr int kPoolSlab = 16;
+
+int16_t *chunk_take(tsdf_map *m)
+{
+    if (m->pool_free.empty()) {
+        void *p = nullptr;
+        const size_t bytes = (size_t)kPoolSlab * 2 * kChunkVox * sizeof(int16_t);
+        if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+        m->pool_slabs.push_back(p);
+        for (int k = kPoolSlab - 1; k >= 0; --k) m->pool_free.push_back((int16_t *)p + (size_t)k * 2 * kChunkVox);
+    }
+    int16_t *b = m->pool_free.back();
+    m->pool_free.pop_back();
+    return b;
+}
+
+void chunk_give(tsdf_map *m, Chunk &c)
+{
+    if (c.buf) m->pool_free.push_back(c.buf);
+    c.buf = nullptr;
+}
+
+// Staging of whole-chunk shifts: kShiftChunks chunks out and kShiftChunks in
+// per round trip (one chunk layer of a 512 x 512 x 128 window).
+constexpr int kShiftChunks = 16;
+
+tsdf_status ensure_chunk_stage(tsdf_map *m)
+{
+    if (m->cstage_dev && m->cflags_dev && m->cflags_host && m->clist_dev && m->clist_host && m->copy_stream &&
+        m->copy_done)
+        return TSDF_OK;
+    if (m->cstage_dev) return TSDF_ENOMEM;  // an earlier attempt failed part way
+    const size_t bytes = (size_t)2 * kShiftChunks * 2 * kChunkVox * sizeof(int16_t);
+    if (hipMalloc(&m->cstage_dev, bytes) != hipSuccess) {
+        m->cstage_dev = nullptr;
+        return TSDF_ENOMEM;
+    }
+    bool ok = hipMalloc(&m->cflags_dev, kShiftChunks * sizeof(uint32_t)) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&m->cflags_host, kShiftChunks * sizeof(uint32_t), hipHostMallocDefault) ==
+                   hipSuccess;
+    ok = ok && hipMalloc(&m->clist_dev, 2 * kShiftChunks * sizeof(BoxXfer)) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&m->clist_host, 2 * kShiftChunks * sizeof(BoxXfer), hipHostMallocDefault) ==
+                   hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&m->copy_stream, hipStreamNonBlocking) == hipSuccess;  // default priority
+    ok = ok && hipEventCreateWithFlags(&m->copy_done, hipEventDisableTiming) == hipSuccess;
+    return ok ? TSDF_OK : TSDF_ENOMEM;
+}
+
 void release(tsdf_map *m)
 {
     if (!m) return;
@@ -172,6 +223,16 @@ void release(tsdf_map *m)
     if (m->interp_ctr) (void)hipFree(m->interp_ctr);
     if (m->interp_ctr_host) (void)hipHostFree(m->interp_ctr_host);
     if (m->interp_pts) (void)hipFree(m->interp_pts);
+    if (m->copy_stream) (void)hipStreamSynchronize(m->copy_stream);
+    if (m->cstage_dev) (void)hipFree(m->cstage_dev);
+    if (m->cflags_dev) (void)hipFree(m->cflags_dev);
+    if (m->cflags_host) (void)hipHostFree(m->cflags_host);
+    if (m->clist_dev) (void)hipFree(m->clist_dev);
+    if (m->clist_host) (void)hipHostFree(m->clist_host);
+    if (m->copy_done) (void)hipEventDestroy(m->copy_done);
+    if (m->copy_stream) (void)hipStreamDestroy(m->copy_stream);
+    m->store.clear();
+    for (void *p : m->pool_slabs) (void)hipHostFree(p);
     prof_clear(m);
     for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
     if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
@@ -981,8 +1042,88 @@ tsdf_status tsdf_shift(tsdf_map *m, const int32_t new_origin[3])
     for (auto &b : leaving) chunk_pieces(b, lp);
     for (auto &b : entering) chunk_pieces(b, ep);
 
-    // 1. leaving voxels: pack (and clear their slots) -> host -> store
-    tsdf_status st = for_batches(m, lp, [&](const std::vector<Box> &batch, int32_t nb, int64_t total, int64_t maxv) {
+    // Whole chunks cross the host link as one copy each, in the store's own
+    // layout, when every (x, y) row of the window holds a chunk's z-run
+    // contiguously (dims multiples of 64, 16-byte aligned arrays); other
+    // pieces go through the general staging path. Entering voxels take the
+    // slots that leaving voxels free, so every write into the window comes
+    // after every read: leaving chunks and pieces first, then entering ones.
+    const bool chunked = m->d.dims[0] % kChunk == 0 && m->d.dims[1] % kChunk == 0 && m->d.dims[2] % kChunk == 0 &&
+                         (uintptr_t)m->sdf % 16 == 0 && (uintptr_t)m->w % 16 == 0;
+    std::vector<Box> lfull, lpart, efull, epart;
+    for (auto &b : lp) (chunked && b.count() == kChunkVox ? lfull : lpart).push_back(b);
+    for (auto &b : ep) {
+        if (!m->store.count(key_of(b.lo))) continue;  // never stored: its slots were cleared on leaving
+        (chunked && b.count() == kChunkVox ? efull : epart).push_back(b);
+    }
+    tsdf_status st = TSDF_OK;
+    if (!lfull.empty() || !efull.empty()) {
+        st = ensure_chunk_stage(m);
+        if (st != TSDF_OK) return st;
+    }
+    int16_t *cs_out = m->cstage_dev, *cs_in = m->cstage_dev + (size_t)kShiftChunks * 2 * kChunkVox;
+    const size_t chunk_bytes = (size_t)2 * kChunkVox * sizeof(int16_t);
+    // the first round of entering chunks goes to the device on the copy
+    // stream right away, while the leaving chunks are packed and copied out
+    auto copy_in = [&](size_t e0) -> tsdf_status {
+        const size_t n = std::min<size_t>(kShiftChunks, efull.size() - e0);
+        for (size_t j = 0; j < n; ++j) {
+            const Chunk &c = m->store.find(key_of(efull[e0 + j].lo))->second;
+            HIPCHK(m, hipMemcpyAsync(cs_in + j * 2 * kChunkVox, c.buf, chunk_bytes, hipMemcpyHostToDevice,
+                                     m->copy_stream));
+        }
+        HIPCHK(m, hipEventRecord(m->copy_done, m->copy_stream));
+        return TSDF_OK;
+    };
+    if (!efull.empty() && (st = copy_in(0)) != TSDF_OK) return st;
+
+    // 1. whole leaving chunks: pack (and clear) on the device, flags of the
+    //    chunks that hold an observed voxel, one copy out per such chunk
+    for (size_t l0 = 0; l0 < lfull.size(); l0 += kShiftChunks) {
+        const int32_t n = (int32_t)std::min<size_t>(kShiftChunks, lfull.size() - l0);
+        for (int32_t j = 0; j < n; ++j) {
+            BoxXfer &x = m->clist_host[j];
+            for (int a = 0; a < 3; ++a) {
+                x.lo[a] = lfull[l0 + j].lo[a];
+                x.ext[a] = kChunk;
+            }
+            x.off = 0;
+        }
+        HIPCHK(m, hipMemcpyAsync(m->clist_dev, m->clist_host, (size_t)n * sizeof(BoxXfer), hipMemcpyHostToDevice,
+                                 m->stream));
+        HIPCHK(m, launch_fill_u32(m->cflags_dev, n, 0u, m->stream));
+        HIPCHK(m, prof_start(m, TSDF_KERNEL_PACK));
+        HIPCHK(m, launch_pack_chunks(m->clist_dev, n, m->sdf, m->w, m->d.dims, cs_out, m->cflags_dev, m->stream));
+        HIPCHK(m, prof_stop(m, TSDF_KERNEL_PACK));
+        HIPCHK(m, hipMemcpyAsync(m->cflags_host, m->cflags_dev, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                 m->stream));
+        HIPCHK(m, hipStreamSynchronize(m->stream));
+        for (int32_t j = 0; j < n; ++j) {
+            const ChunkKey ck = key_of(lfull[l0 + j].lo);
+            auto it = m->store.find(ck);
+            if (!m->cflags_host[j]) {
+                // nothing observed: nothing to keep (a stored chunk whose voxels
+                // were all resident holds zeros only)
+                if (it != m->store.end()) {
+                    chunk_give(m, it->second);
+                    m->store.erase(it);
+                }
+                continue;
+            }
+            if (it == m->store.end()) {
+                Chunk c;
+                c.buf = chunk_take(m);
+                if (!c.buf) return TSDF_ENOMEM;
+                it = m->store.emplace(ck, c).first;
+            }
+            HIPCHK(m, hipMemcpyAsync(it->second.buf, cs_out + (size_t)j * 2 * kChunkVox, chunk_bytes,
+                                     hipMemcpyDeviceToHost, m->stream));
+        }
+        HIPCHK(m, hipStreamSynchronize(m->stream));
+    }
+
+    // 2. other leaving pieces: pack (and clear) -> host staging -> store
+    st = for_batches(m, lpart, [&](const std::vector<Box> &batch, int32_t nb, int64_t total, int64_t maxv) {
         tsdf_status s = stage_out(m, nb, total, maxv, true);
         if (s != TSDF_OK) return s;
         const int16_t *hs = m->stage_host, *hw = m->stage_host + m->stage_cap;
@@ -995,9 +1136,10 @@ tsdf_status tsdf_shift(tsdf_map *m, const int32_t new_origin[3])
             if (it == m->store.end()) {
                 if (all_zero(hs + off, hw + off, cnt)) continue;  // nothing observed: nothing to keep
                 Chunk c;
-                c.sdf.assign(kChunkVox, 0);
-                c.w.assign(kChunkVox, 0);
-                it = m->store.emplace(ck, std::move(c)).first;
+                c.buf = chunk_take(m);
+                if (!c.buf) return TSDF_ENOMEM;
+                memset(c.buf, 0, (size_t)2 * kChunkVox * sizeof(int16_t));
+                it = m->store.emplace(ck, c).first;
             }
             Chunk &c = it->second;
             const int32_t ey = b.hi[1] - b.lo[1], ez = b.hi[2] - b.lo[2];
@@ -1005,19 +1147,43 @@ tsdf_status tsdf_shift(tsdf_map *m, const int32_t new_origin[3])
                 for (int32_t y = b.lo[1]; y < b.hi[1]; ++y) {
                     const int64_t src = off + ((int64_t)(x - b.lo[0]) * ey + (y - b.lo[1])) * ez;
                     const int64_t dst = chunk_off(x, y, b.lo[2]);
-                    memcpy(&c.sdf[dst], hs + src, (size_t)ez * sizeof(int16_t));
-                    memcpy(&c.w[dst], hw + src, (size_t)ez * sizeof(int16_t));
+                    memcpy(c.sdf() + dst, hs + src, (size_t)ez * sizeof(int16_t));
+                    memcpy(c.w() + dst, hw + src, (size_t)ez * sizeof(int16_t));
                 }
         }
         return TSDF_OK;
     });
     if (st != TSDF_OK) return st;
 
-    // 2. entering voxels held by the store: store -> host staging -> unpack
-    std::vector<Box> present;
-    for (auto &b : ep)
-        if (m->store.count(key_of(b.lo))) present.push_back(b);
-    st = for_batches(m, present, [&](const std::vector<Box> &batch, int32_t nb, int64_t total, int64_t maxv) {
+    // 3. whole entering chunks held by the store: already on their way to the
+    //    device (copy stream); unpacked once there, then dropped from the store
+    for (size_t e0 = 0; e0 < efull.size(); e0 += kShiftChunks) {
+        const int32_t n = (int32_t)std::min<size_t>(kShiftChunks, efull.size() - e0);
+        if (e0 > 0 && (st = copy_in(e0)) != TSDF_OK) return st;
+        BoxXfer *list = m->clist_host + kShiftChunks;
+        for (int32_t j = 0; j < n; ++j) {
+            for (int a = 0; a < 3; ++a) {
+                list[j].lo[a] = efull[e0 + j].lo[a];
+                list[j].ext[a] = kChunk;
+            }
+            list[j].off = 0;
+        }
+        HIPCHK(m, hipMemcpyAsync(m->clist_dev + kShiftChunks, list, (size_t)n * sizeof(BoxXfer),
+                                 hipMemcpyHostToDevice, m->stream));
+        HIPCHK(m, hipStreamWaitEvent(m->stream, m->copy_done, 0));
+        HIPCHK(m, prof_start(m, TSDF_KERNEL_UNPACK));
+        HIPCHK(m, launch_unpack_chunks(m->clist_dev + kShiftChunks, n, m->sdf, m->w, m->d.dims, cs_in, m->stream));
+        HIPCHK(m, prof_stop(m, TSDF_KERNEL_UNPACK));
+        HIPCHK(m, hipStreamSynchronize(m->stream));
+        for (int32_t j = 0; j < n; ++j) {
+            auto it = m->store.find(key_of(efull[e0 + j].lo));
+            chunk_give(m, it->second);
+            m->store.erase(it);
+        }
+    }
+
+    // 4. other entering pieces held by the store: store -> host staging -> unpack
+    st = for_batches(m, epart, [&](const std::vector<Box> &batch, int32_t nb, int64_t total, int64_t maxv) {
         int16_t *hs = m->stage_host, *hw = m->stage_host + m->stage_cap;
         for (int32_t k = 0; k < nb; ++k) {
             const Box &b = batch[k];
@@ -1029,13 +1195,16 @@ tsdf_status tsdf_shift(tsdf_map *m, const int32_t new_origin[3])
                 for (int32_t y = b.lo[1]; y < b.hi[1]; ++y) {
                     const int64_t dst = off + ((int64_t)(x - b.lo[0]) * ey + (y - b.lo[1])) * ez;
                     const int64_t src = chunk_off(x, y, b.lo[2]);
-                    memcpy(hs + dst, &c.sdf[src], (size_t)ez * sizeof(int16_t));
-                    memcpy(hw + dst, &c.w[src], (size_t)ez * sizeof(int16_t));
+                    memcpy(hs + dst, c.sdf() + src, (size_t)ez * sizeof(int16_t));
+                    memcpy(hw + dst, c.w() + src, (size_t)ez * sizeof(int16_t));
                     // popped: the store no longer holds these voxels
-                    memset(&c.sdf[src], 0, (size_t)ez * sizeof(int16_t));
-                    memset(&c.w[src], 0, (size_t)ez * sizeof(int16_t));
+                    memset(c.sdf() + src, 0, (size_t)ez * sizeof(int16_t));
+                    memset(c.w() + src, 0, (size_t)ez * sizeof(int16_t));
                 }
-            if (b.count() == kChunkVox) m->store.erase(it);
+            if (b.count() == kChunkVox) {
+                chunk_give(m, c);
+                m->store.erase(it);
+            }
         }
         int16_t *dsdf = m->stage_dev, *dw = m->stage_dev + m->stage_cap;
         HIPCHK(m, hipMemcpyAsync(m->boxes_dev, m->boxes_host, (size_t)nb * sizeof(BoxXfer), hipMemcpyHostToDevice,
@@ -1082,8 +1251,8 @@ tsdf_status tsdf_readback(tsdf_map *m, const int32_t lo[3], const int32_t hi[3],
                     memset(w_out + dst, 0, nb);
                 } else {
                     const int64_t src = chunk_off(x, y, b.lo[2]);
-                    memcpy(sdf_out + dst, &it->second.sdf[src], nb);
-                    memcpy(w_out + dst, &it->second.w[src], nb);
+                    memcpy(sdf_out + dst, it->second.sdf() + src, nb);
+                    memcpy(w_out + dst, it->second.w() + src, nb);
                 }
             }
     }

@@ -18,8 +18,9 @@
 #define __forceinline__ inline
 #define __fma_rn(a, b, c) std::fma((a), (b), (c))
 #define __dmul_rn(a, b) ((a) * (b))
-static double g_pert = 0.0;
+static double g_pert = 0.0, g_rsq_pert = 0.0;
 #define __builtin_amdgcn_rcp(x) ((1.0 / (x)) * (1.0 + g_pert))
+#define __builtin_amdgcn_rsq(x) ((1.0 / std::sqrt(x)) * (1.0 + g_rsq_pert))
 using std::fabs;
 using std::floor;
 using std::fmin;
@@ -34,9 +35,11 @@ int main(int argc, char **argv)
     std::mt19937_64 rng(argc > 1 ? strtoull(argv[1], nullptr, 10) : 7);
     const int iters = argc > 2 ? atoi(argv[2]) : 20000;
     const double perts[] = {0.0, 0x1p-20, -0x1p-20, 0x1p-14, -0x1p-14, 0x1p-30, -0x1p-45};
+    const double rsq_perts[] = {0.0, 0x1p-18, -0x1p-18, 0x1p-22, -0x1p-22};
     long bad = 0, vox = 0, ties = 0, rays = 0;
     for (int it = 0; it < iters; ++it) {
         g_pert = perts[it % 7];
+        g_rsq_pert = rsq_perts[it % 5];
         RayParams P{};
         const int64_t lim = 1ll << std::uniform_int_distribution<int>(0, 31)(rng);
         int32_t q[3];
@@ -52,6 +55,33 @@ int main(int argc, char **argv)
         Ray R;
         if (!make_ray(q, P, R)) continue;
         ++rays;
+        // the ray itself against exact integers: r = floor(sqrt(|D|^2)),
+        // off = rdiv(tau D, r), E = q + off, S = q - off (S = o for r <= tau)
+        // (for reciprocal errors within what make_ray's divisions assume)
+        if (fabs(g_pert) <= 0x1p-20) {
+            unsigned __int128 dd = 0;
+            __int128 D[3];
+            for (int a = 0; a < 3; ++a) {
+                D[a] = (__int128)q[a] - P.o[a];
+                dd += (unsigned __int128)(D[a] * D[a]);
+            }
+            unsigned __int128 rr = (unsigned __int128)std::sqrt((long double)dd);
+            while (rr * rr > dd) --rr;
+            while ((rr + 1) * (rr + 1) <= dd) ++rr;
+            bool ok = (double)(uint64_t)rr == R.r;
+            for (int a = 0; a < 3 && ok; ++a) {
+                const __int128 num = (__int128)P.tau * D[a];
+                const __int128 an = num < 0 ? -num : num;
+                __int128 off = (2 * an + (__int128)rr) / (2 * (__int128)rr);
+                if (num < 0) off = -off;
+                ok = R.E[a] == q[a] + (int64_t)off &&
+                     R.S[a] == ((__int128)rr <= P.tau ? (int64_t)P.o[a] : q[a] - (int64_t)off);
+            }
+            if (!ok) {
+                if (bad < 5) printf("ray mismatch: |D|^2 = %.17g r = %.17g\n", (double)dd, R.r);
+                ++bad;
+            }
+        }
         Ray Rk = R;
         Rk.inv_r2 = refined_rcp(Rk.r2);
         const uint32_t i = (uint32_t)rng();

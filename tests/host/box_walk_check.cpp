@@ -20,6 +20,7 @@
 #define __fma_rn(a, b, c) std::fma((a), (b), (c))
 #define __dmul_rn(a, b) ((a) * (b))
 #define __builtin_amdgcn_rcp(x) (1.0 / (x))
+#define __builtin_amdgcn_rsq(x) (1.0 / std::sqrt(x))
 using std::fabs;
 using std::floor;
 using std::fmin;
@@ -38,7 +39,7 @@ int main(int argc, char **argv)
 {
     std::mt19937_64 rng(argc > 1 ? strtoull(argv[1], nullptr, 10) : 11);
     const int iters = argc > 2 ? atoi(argv[2]) : 20000;
-    long bad = 0, tiles = 0, visits = 0, rays = 0;
+    long bad = 0, tiles = 0, visits = 0, rays = 0, resumes = 0, direct = 0;
     int32_t max_count = 0;
     for (int it = 0; it < iters; ++it) {
         RayParams P{};
@@ -122,12 +123,36 @@ int main(int argc, char **argv)
                 Walk X;
                 walk_init(R, X);
                 walk_advance(X, c);
+                {
+                    bool in_box = true;
+                    for (int a = 0; a < 3; ++a) in_box = in_box && X.g[a] >= blo[a] && X.g[a] < bhi[a];
+                    direct += in_box ? 1 : 0;
+                }
                 std::vector<std::pair<int32_t, double>> got;
+                // the tile pass's direct resume from the entry record must
+                // give exactly the state of the general steps
+                BoxWalk Vd;
+                Ray Rd;
+                const int32_t offd[3] = {R.E[0] - R.q[0], R.E[1] - R.q[1], R.E[2] - R.q[2]};
+                const bool okd = box_walk_resume(R.q, offd, (uint32_t)R.r, c, P.o, P.tau, blo, bhi, sh, 0u, Rd, Vd);
+                ++resumes;
                 if (walk_enter_box(X, blo, bhi)) {
                     BoxWalk V;
                     box_walk_from(X, blo, bhi, sh, 0u, V);
+                    bool same = okd && Vd.lim == V.lim && Vd.n == V.n && Vd.lv == V.lv;
+                    for (int a = 0; a < 3; ++a)
+                        same = same && Vd.T[a] == V.T[a] && Vd.dT[a] == V.dT[a] && Vd.dn[a] == V.dn[a] &&
+                               Vd.dlv[a] == V.dlv[a] && Rd.S[a] == R.S[a] && Rd.E[a] == R.E[a] && Rd.D[a] == R.D[a];
+                    same = same && Rd.r == R.r && Rd.r2 == R.r2;
+                    if (!same) {
+                        if (bad < 5) printf("direct resume differs: ray %d tile (%d %d %d)\n", it, T.g[0], T.g[1], T.g[2]);
+                        ++bad;
+                    }
                     do got.push_back({V.lv, V.n});
                     while (box_walk_next(V) && got.size() < 100000);
+                } else if (okd) {
+                    if (bad < 5) printf("direct resume enters a box the walk misses: ray %d\n", it);
+                    ++bad;
                 }
                 bool ok = got.size() == want.size();
                 for (size_t k = 0; ok && k < got.size(); ++k) {
@@ -155,7 +180,7 @@ int main(int argc, char **argv)
             }
         }
     }
-    printf("rays %ld tiles %ld visits %ld largest crossing count %d mismatches %ld\n", rays, tiles, visits, max_count,
-           bad);
+    printf("rays %ld tiles %ld resumes %ld (direct %ld) visits %ld largest crossing count %d mismatches %ld\n", rays,
+           tiles, resumes, direct, visits, max_count, bad);
     return bad != 0 || visits == 0;
 }

@@ -21,6 +21,7 @@
 #define __fma_rn(a, b, c) std::fma((a), (b), (c))
 #define __dmul_rn(a, b) ((a) * (b))
 #define __builtin_amdgcn_rcp(x) (1.0 / (x))
+#define __builtin_amdgcn_rsq(x) (1.0 / std::sqrt(x))
 using std::fabs;
 using std::floor;
 using std::fmin;
