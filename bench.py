@@ -384,6 +384,7 @@ def uneven_batch_leg(torch, synth, reps: int = 3):
         if tiling:
             for m in ms:
                 m.set_tiling(tiling, best["workgroups"])
+                m.set_blocks(best["bin_block"], best["tile_block"])
         return ms
 
     def timed(form, tiling):
@@ -418,7 +419,8 @@ def uneven_batch_leg(torch, synth, reps: int = 3):
     timed("plain", None)
     t_all, t_16, t_plain = timed("all", lt), timed("per16", lt), timed("plain", None)
     return {"scans": 256, "points": int(sum(d.shape[0] for d in dev)), "voxel_updates": upd,
-            "autotuned": {"lt": list(lt), "workgroups": best["workgroups"]},
+            "autotuned": {"lt": list(lt), "workgroups": best["workgroups"], "bin_block": best["bin_block"],
+                          "tile_block": best["tile_block"]},
             "one_launch": {"scans_per_s": 256 / t_all, "voxel_updates_per_s": upd / t_all, "ms": 1e3 * t_all},
             "launch_per_16": {"scans_per_s": 256 / t_16, "voxel_updates_per_s": upd / t_16, "ms": 1e3 * t_16},
             "plain": {"scans_per_s": 256 / t_plain, "voxel_updates_per_s": upd / t_plain, "ms": 1e3 * t_plain}}
@@ -550,6 +552,11 @@ def main():
     ap.add_argument("--carve-only", action="store_true",
                     help="with --profile-only: the carving path on the config-2 sequence only")
     ap.add_argument("--serving-seconds", type=float, default=10.0, help="real-time replay length (seconds)")
+    ap.add_argument("--blocks", type=str, default="",
+                    help="binning block and tile workgroup sizes for the main map, e.g. 512,256 (default: the "
+                         "library's)")
+    ap.add_argument("--tiling", type=str, default="",
+                    help="log2 tile edges for the main map, e.g. 3,3,3 (default: the library's)")
     ap.add_argument("--prewarm-seconds", type=float, default=2.0,
                     help="untimed batched steps before any timed leg (the device clocks up)")
     ap.add_argument("--profile-only", action="store_true", help="warmup + timed steps only (for rocprofv3)")
@@ -597,6 +604,10 @@ def main():
     # timing events all live on it
     stream = torch.cuda.Stream()
     gm = TsdfMap.from_spec(spec, stream=stream)
+    if args.blocks:
+        gm.set_blocks(*[int(v) for v in args.blocks.split(",")])
+    if args.tiling:
+        gm.set_tiling(tuple(int(v) for v in args.tiling.split(",")))
 
     batch_items = [(gm, x, p) for x, p in zip(dev, poses)]
 

@@ -308,6 +308,16 @@ tsdf_status tsdf_mesh(tsdf_map *m, const int32_t lo[3], const int32_t hi[3], flo
  * and so every result, is the same for every tiling. */
 tsdf_status tsdf_map_set_tiling(tsdf_map *m, const int32_t log2_tile[3], int32_t tile_workgroups);
 tsdf_status tsdf_map_get_tiling(const tsdf_map *m, int32_t log2_tile[3], int32_t *tile_workgroups);
+
+/* Block sizes of the integration kernels: bin_block threads per binning
+ * block, one scan point each (128, 256 or 512; a block's rays share one LDS
+ * table of tile counts), and tile_block threads per tile workgroup (256 or
+ * 512; a workgroup holds about 32 KB of candidate keys per 256 threads).
+ * 0 selects the default (256 for both); tsdf_map_get_blocks reports the
+ * sizes in use. A batch uses its first scan's map's. The arithmetic, and so
+ * every result, is the same for every choice; TSDF_EINVAL for other sizes. */
+tsdf_status tsdf_map_set_blocks(tsdf_map *m, int32_t bin_block, int32_t tile_block);
+tsdf_status tsdf_map_get_blocks(const tsdf_map *m, int32_t *bin_block, int32_t *tile_block);
 tsdf_status tsdf_profile_read(tsdf_map *m, int32_t kernel, double *total_ms, int64_t *launches);
 const char *tsdf_kernel_name(int32_t kernel);
 

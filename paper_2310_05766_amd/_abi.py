@@ -23,7 +23,7 @@ EXPORTS = (
     "tsdf_map_get_tiling", "tsdf_batch_release", "tsdf_set_graph_launch", "tsdf_batch_profile",
     "tsdf_batch_profile_read", "tsdf_map_set_interpolation", "tsdf_map_get_interpolation", "tsdf_mesh",
     "tsdf_register_scan", "tsdf_register_sums", "tsdf_map_set_carving", "tsdf_map_get_carving",
-    "tsdf_map_key_atomics", "tsdf_integrate_scan_noalloc",
+    "tsdf_map_key_atomics", "tsdf_integrate_scan_noalloc", "tsdf_map_set_blocks", "tsdf_map_get_blocks",
 )
 KERNELS = {"k_bin": 0, "k_tile": 1, "k_pack": 2, "k_unpack": 3}
 
@@ -100,6 +100,10 @@ def lib():
     L.tsdf_map_get_carving.argtypes = [vp, C.POINTER(C.c_int32)]
     L.tsdf_integrate_scan_noalloc.restype = st
     L.tsdf_integrate_scan_noalloc.argtypes = [vp, vp, i64, C.POINTER(C.c_double), C.POINTER(ScanStats)]
+    L.tsdf_map_set_blocks.restype = st
+    L.tsdf_map_set_blocks.argtypes = [vp, C.c_int32, C.c_int32]
+    L.tsdf_map_get_blocks.restype = st
+    L.tsdf_map_get_blocks.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.tsdf_map_key_atomics.restype = st
     L.tsdf_map_key_atomics.argtypes = [vp, C.POINTER(C.c_int64)]
     L.tsdf_integrate_batch.restype = st

@@ -27,7 +27,6 @@ namespace tsdf {
 
 namespace {
 
-constexpr int kTileBlock = 256;
 constexpr int kAllocBlock = 1024;
 
 __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
@@ -54,7 +53,7 @@ __device__ __forceinline__ uint4 entry_ray(const Ray &R, uint32_t cpack)
     return make_uint4((uint32_t)R.r, o0 | o1 << 16, o2 | (cpack & 0xffffu) << 16, cpack >> 16);
 }
 
-template <bool kFill>
+template <bool kFill, int kBinBlock>
 __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
 {
     __shared__ uint32_t h_key[kHashSlots];  // key + 1; 0 = free
@@ -230,8 +229,19 @@ __global__ __launch_bounds__(kAllocBlock) void k_alloc(BatchArrays B)
 #pragma unroll
     for (int j = 0; j < kAllocPer; ++j) cs[j] = (t < H.gtiles && s_lo + j < s_hi) ? cs[j] : 0u;
     uint32_t c = 0;
+    uint64_t busy = 0;  // this part's busy sequence slots
 #pragma unroll
-    for (int j = 0; j < kAllocPer; ++j) c += cs[j];
+    for (int j = 0; j < kAllocPer; ++j) {
+        c += cs[j];
+        busy |= cs[j] ? 1ull << (s_lo + j) : 0ull;
+    }
+    // the tile's busy slots: the four parts' masks together
+#pragma unroll
+    for (int x = 1; x < 4; x <<= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)busy, x);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(busy >> 32), x);
+        busy |= (uint64_t)lo | (uint64_t)hi << 32;
+    }
     // inclusive prefix of the four parts of a tile, and the tile's total
     uint32_t pq = c;
     {
@@ -294,8 +304,7 @@ __global__ __launch_bounds__(kAllocBlock) void k_alloc(BatchArrays B)
         if (part == 0u) {
             const uint32_t slot =
                 heavy ? s_base[1] + s_w[1][wave] + pn - 1u : H.gtiles - 1u - (s_base[2] + s_w[2][wave] + pl - 1u);
-            B.nonempty[slot] = t;
-            B.nonempty_map[slot] = (uint32_t)map_of_tile(B, H.nmaps, t);
+            B.jobs[slot] = make_uint4(t, (uint32_t)map_of_tile(B, H.nmaps, t), (uint32_t)busy, (uint32_t)(busy >> 32));
         }
     }
 }
@@ -410,22 +419,27 @@ __device__ __forceinline__ MapDev uniform_map(const MapDev &m)
 // Persistent tile pass. Workgroup b first takes busy tile b, then pulls
 // further tiles from queue b % nq, nq = min(8, workgroups) (one queue per
 // XCD keeps same-address atomics spread; with fewer than 8 workgroups each
-// queue still has one, so every job is reached). Per tile, the busy sequence slots are taken in groups of
-// G: the candidates of a group's runs are computed together, one LDS key
-// buffer per slot, then each voxel applies the group's scans in submission
-// order. A tile busy in several slots keeps its SDF and weights in LDS.
+// queue still has one, so every job is reached). A tile's job record holds
+// its map and its busy sequence slots, so that the runs and the map record
+// of a tile are requested together, and a group's sensors come from a table
+// indexed by (map, sequence slot). Per tile, the busy sequence slots are
+// taken in groups of G: the candidates of a group's runs are computed
+// together, one LDS key buffer per slot, then each voxel applies the group's
+// scans in submission order. A tile busy in several slots keeps its SDF and
+// weights in LDS.
 // At most 96 VGPRs: five waves per SIMD, the most this kernel holds without
 // spilling.
+template <int kTileBlock>
 __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_tile(BatchArrays B)
 {
     extern __shared__ uint64_t s_keys[];  // G * tvox keys, then the cached tile: tvox sdf, tvox w
+    // per busy slot of the tile, in sequence order: first entry, entries,
+    // sequence slot; per slot of the current group: sensor (o, tau)
     __shared__ uint32_t s_beg[kMaxSeq], s_cnt[kMaxSeq];
-    __shared__ int32_t s_scan[kMaxSeq];
-    __shared__ int32_t s_o[kMaxGroup][3], s_tau[kMaxGroup];
-    __shared__ uint32_t s_gbeg[kMaxGroup];  // the group's runs: first entry
+    __shared__ uint8_t s_list[kMaxSeq];
+    __shared__ int4 s_sens[kMaxGroup];
     __shared__ uint32_t s_vis[kMaxGroup], s_upd[kMaxGroup];
-    __shared__ uint32_t s_busy, s_job;
-    __shared__ uint8_t s_list[kMaxSeq];  // the tile's busy sequence slots, in order
+    __shared__ uint32_t s_job;
     const BatchHdr H = *B.hdr;
     const int32_t lsum = H.lt[0] + H.lt[1] + H.lt[2];
     const uint32_t tvox = 1u << lsum;
@@ -444,25 +458,20 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
     for (uint32_t v = threadIdx.x; v < (uint32_t)G * tvox; v += kTileBlock) s_keys[v] = kEmptyKey;
     while (job < nne) {
         const uint32_t at = job < nheavy ? job : H.gtiles - 1u - (job - nheavy);
-        const uint32_t g = uniform(B.nonempty[at]);
-        const int32_t mb = uniform((int32_t)B.nonempty_map[at]);
-        // the tile's runs, one load per sequence slot, all in flight
-        // together; the first wave (at most 64 slots) lists the busy slots in
+        const uint4 jb = B.jobs[at];
+        const uint32_t g = uniform(jb.x);
+        const int32_t mb = uniform((int32_t)jb.y);
+        const uint64_t busy = (uint64_t)uniform(jb.z) | (uint64_t)uniform(jb.w) << 32;
+        const int nbusy = __popcll(busy);
+        // the busy slots' runs and sensors, all in flight together, listed in
         // order, so that groups of G hold busy slots only
-        uint32_t c = 0;
-        if (threadIdx.x < (uint32_t)H.S) {
+        if (threadIdx.x < 64u && ((busy >> threadIdx.x) & 1ull)) {
             const uint32_t k = threadIdx.x * H.gtiles + g;
-            c = B.counts[k];
-            s_cnt[threadIdx.x] = c;
-            s_beg[threadIdx.x] = c ? B.offsets[k] : 0u;
-            s_scan[threadIdx.x] = c ? B.seq_scan[mb * H.S + threadIdx.x] : -1;
+            const int p = __popcll(busy & ((1ull << threadIdx.x) - 1ull));
+            s_cnt[p] = B.counts[k];
+            s_beg[p] = B.offsets[k];
+            s_list[p] = (uint8_t)threadIdx.x;
         }
-        if (threadIdx.x < 64u) {
-            const uint64_t bm = __ballot(c != 0u);
-            if (c) s_list[__popcll(bm & ((1ull << threadIdx.x) - 1ull))] = (uint8_t)threadIdx.x;
-            if (threadIdx.x == 0) s_busy = (uint32_t)__popcll(bm);
-        }
-        __syncthreads();
         const MapDev MD = uniform_map(B.maps[mb]);
         const uint32_t t = g - MD.tile_base;
         const uint32_t tz = t % (uint32_t)MD.nt[2];
@@ -477,7 +486,7 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
             bhi[a] = MD.origin[a] + min(t0[a] + (1 << H.lt[a]), MD.dims[a]);
         }
         __syncthreads();
-        const bool cached = uniform(s_busy) > 1u;
+        const bool cached = nbusy > 1;
         if (cached) {
             for (uint32_t v = threadIdx.x; v < tvox; v += kTileBlock) {
                 const int32_t rz = (int32_t)(v & (ez - 1)) + t0[2];
@@ -490,7 +499,6 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                 c_w[v] = wv;
             }
         }
-        const int nbusy = (int)uniform(s_busy);
         for (int j0 = 0; j0 < nbusy; j0 += G) {
             // a group: busy slots j0 .. j0 + ng - 1 of the list, in order
             const int ng = min(G, nbusy - j0);
@@ -500,20 +508,14 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
             uint32_t gsum = 0;
 #pragma unroll
             for (int r = 0; r < kMaxGroup; ++r) {
-                if (r < ng) gsum += s_cnt[s_list[j0 + r]];
+                if (r < ng) gsum += s_cnt[j0 + r];
                 pre[r] = uniform(gsum);
             }
             gsum = uniform(gsum);
             if (threadIdx.x < (uint32_t)ng) {
-                const int r = (int)threadIdx.x;
-                s_vis[r] = 0;
-                s_upd[r] = 0;
-                s_gbeg[r] = s_beg[s_list[j0 + r]];
-                const ScanDev &SD = B.scans[s_scan[s_list[j0 + r]]];
-                s_o[r][0] = SD.rp.o[0];
-                s_o[r][1] = SD.rp.o[1];
-                s_o[r][2] = SD.rp.o[2];
-                s_tau[r] = SD.rp.tau;
+                s_vis[threadIdx.x] = 0;
+                s_upd[threadIdx.x] = 0;
+                s_sens[threadIdx.x] = B.seq_sensor[mb * H.S + (int32_t)s_list[j0 + threadIdx.x]];
             }
             __syncthreads();
             for (uint32_t e = threadIdx.x; e < gsum; e += kTileBlock) {
@@ -528,14 +530,15 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                     base = past ? pre[k] : base;
                 }
                 const uint32_t ee = e - base;
-                const uint32_t beg = s_gbeg[r];
+                const uint32_t beg = s_beg[j0 + r];
                 // the run lies inside the entry buffer unless the fill overflowed
                 if (beg + ee >= H.cap) continue;
                 const uint4 ra = B.entries[beg + ee];
                 const uint4 rb = B.entries2[beg + ee];
                 const uint32_t i = ra.x;
-                const int32_t o[3] = {s_o[r][0], s_o[r][1], s_o[r][2]};
-                const int32_t tau = s_tau[r];
+                const int4 sens = s_sens[r];
+                const int32_t o[3] = {sens.x, sens.y, sens.z};
+                const int32_t tau = sens.w;
                 const int32_t q[3] = {(int32_t)ra.y, (int32_t)ra.z, (int32_t)ra.w};
                 const int32_t off[3] = {(int16_t)(rb.y & 0xffffu), (int16_t)(rb.y >> 16), (int16_t)(rb.z & 0xffffu)};
                 const int32_t c[3] = {(int32_t)((rb.z >> 16) & 0xffu), (int32_t)(rb.z >> 24), (int32_t)(rb.w & 0xffu)};
@@ -609,7 +612,7 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
             }
             __syncthreads();
             if (threadIdx.x < (uint32_t)ng) {
-                const uint32_t k = (uint32_t)s_list[j0 + threadIdx.x] * H.gtiles + g;
+                const uint32_t k = (uint32_t)s_list[j0 + threadIdx.x] * H.gtiles + g;  // sequence slot, tile
                 B.counts[k] = 0;  // ready for the next batch
                 if (H.want_stats) {
                     B.tile_vis[k] = s_vis[threadIdx.x];
@@ -655,7 +658,7 @@ __global__ __launch_bounds__(256) void k_stats(BatchArrays B)
         B.tile_vis[k0 + t] = 0;
         B.tile_upd[k0 + t] = 0;
     }
-    const uint32_t nb = (uint32_t)((SD.n + kBinBlock - 1) / kBinBlock);
+    const uint32_t nb = (uint32_t)((SD.n + H.bin_block - 1) / H.bin_block);
     for (uint32_t b = threadIdx.x; b < nb; b += 256) val += B.valid_part[SD.block0 + b];
     s_sum[0][threadIdx.x] = upd;
     s_sum[1][threadIdx.x] = val;
@@ -692,22 +695,48 @@ int32_t max_tiles_per_ray(int32_t tau, const int32_t lt[3])
     return n;
 }
 
+namespace {
+
+template <int kBB>
+void launch_bin(bool fill, uint32_t bins, const BatchArrays &B, hipStream_t stream)
+{
+    if (fill) hipLaunchKernelGGL((k_bin<true, kBB>), dim3(bins), dim3(kBB), 0, stream, B);
+    else hipLaunchKernelGGL((k_bin<false, kBB>), dim3(bins), dim3(kBB), 0, stream, B);
+}
+
+void launch_bin_any(bool fill, uint32_t bins, uint32_t block, const BatchArrays &B, hipStream_t stream)
+{
+    if (block == 128) launch_bin<128>(fill, bins, B, stream);
+    else if (block == 512) launch_bin<512>(fill, bins, B, stream);
+    else launch_bin<256>(fill, bins, B, stream);
+}
+
+}  // namespace
+
+bool launch_blocks_ok(int32_t bin_block, int32_t tile_block)
+{
+    return (bin_block == 128 || bin_block == 256 || bin_block == 512) && (tile_block == 256 || tile_block == 512);
+}
+
 hipError_t launch_batch(const BatchArrays &B, const LaunchCaps &caps, hipStream_t stream, hipEvent_t ev_start,
                         hipEvent_t ev_binned, hipEvent_t ev_tiles)
 {
     hipError_t e;
     if (ev_start && (e = hipEventRecord(ev_start, stream)) != hipSuccess) return e;
     const uint32_t bins = caps.blocks > 0 ? caps.blocks : 1u;
-    hipLaunchKernelGGL(k_bin<false>, dim3(bins), dim3(kBinBlock), 0, stream, B);
+    launch_bin_any(false, bins, caps.bin_block, B, stream);
     hipLaunchKernelGGL(k_alloc, dim3((caps.gtiles + kAllocTiles - 1) / kAllocTiles), dim3(kAllocBlock), 0, stream,
                        B);
-    hipLaunchKernelGGL(k_bin<true>, dim3(bins), dim3(kBinBlock), 0, stream, B);
+    launch_bin_any(true, bins, caps.bin_block, B, stream);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev_binned && (e = hipEventRecord(ev_binned, stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tile, dim3((uint32_t)caps.tile_grid), dim3(kTileBlock), caps.tile_lds, stream, B);
+    if (caps.tile_block == 512)
+        hipLaunchKernelGGL(k_tile<512>, dim3((uint32_t)caps.tile_grid), dim3(512), caps.tile_lds, stream, B);
+    else
+        hipLaunchKernelGGL(k_tile<256>, dim3((uint32_t)caps.tile_grid), dim3(256), caps.tile_lds, stream, B);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev_tiles && (e = hipEventRecord(ev_tiles, stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_stats, dim3(caps.scans > 0 ? caps.scans : 1u), dim3(256), 0, stream, B);
+    if (caps.stats) hipLaunchKernelGGL(k_stats, dim3(caps.scans > 0 ? caps.scans : 1u), dim3(256), 0, stream, B);
     return hipGetLastError();
 }
 

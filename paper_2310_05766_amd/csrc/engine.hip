@@ -19,7 +19,7 @@ size_t up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 // Fixed layout of the descriptor tables for given capacities.
 struct DescLayout {
-    size_t hdr, maps, scans, block_scan, seq_scan, total;
+    size_t hdr, maps, scans, block_scan, seq_sensor, total;
     static DescLayout of(size_t cap_maps, size_t cap_scans, size_t cap_blocks)
     {
         DescLayout L;
@@ -27,8 +27,8 @@ struct DescLayout {
         L.maps = up(sizeof(BatchHdr));
         L.scans = up(L.maps + cap_maps * sizeof(MapDev));
         L.block_scan = up(L.scans + cap_scans * sizeof(ScanDev));
-        L.seq_scan = up(L.block_scan + cap_blocks * sizeof(uint32_t));
-        L.total = up(L.seq_scan + cap_maps * kMaxSeq * sizeof(int32_t));
+        L.seq_sensor = up(L.block_scan + cap_blocks * sizeof(uint32_t));
+        L.total = up(L.seq_sensor + cap_maps * kMaxSeq * sizeof(int4));
         return L;
     }
 };
@@ -86,7 +86,7 @@ size_t single_map_array_bytes(const int32_t dims[3])
 {
     // finest allowed tiles: edges 4, 4, 8
     const size_t g = (size_t)ntiles_axis(dims[0], 2) * ntiles_axis(dims[1], 2) * ntiles_axis(dims[2], 3);
-    return up(5 * g * sizeof(uint32_t)) + 2 * up(g * sizeof(uint32_t));
+    return up(5 * g * sizeof(uint32_t)) + up(g * sizeof(uint4));
 }
 
 Engine::Engine(hipStream_t stream, int device) : stream_(stream), device_(device)
@@ -186,10 +186,11 @@ tsdf_status Engine::profile_read(int stage, double *ms, int64_t *n)
     return TSDF_OK;
 }
 
-tsdf_status Engine::run(const std::vector<MapRef> &maps, const std::vector<ScanRef> &scans, const int32_t lt[3],
-                        int32_t tile_grid, tsdf_scan_stats *stats)
+tsdf_status Engine::run(const std::vector<MapRef> &maps, const std::vector<ScanRef> &scans, const LaunchShape &shape,
+                        tsdf_scan_stats *stats)
 {
     if (poisoned_) return TSDF_EDEVICE;
+    if (!launch_blocks_ok(shape.bin_block, shape.tile_block)) return TSDF_EINVAL;
     // every argument first: nothing is touched for an invalid batch
     for (const ScanRef &s : scans) {
         if (s.map < 0 || (size_t)s.map >= maps.size() || !s.pose || s.n < 0 || s.n > 0xffffffffLL ||
@@ -209,7 +210,7 @@ tsdf_status Engine::run(const std::vector<MapRef> &maps, const std::vector<ScanR
         std::vector<int32_t> per(maps.size(), 0);
         size_t e = b;
         while (e < scans.size() && per[scans[e].map] < kMaxSeq) per[scans[e++].map]++;
-        tsdf_status st = run_chunk(maps, scans, b, e, lt, tile_grid, stats ? stats + b : nullptr);
+        tsdf_status st = run_chunk(maps, scans, b, e, shape, stats ? stats + b : nullptr);
         if (st != TSDF_OK) return st;
         b = e;
     }
@@ -217,8 +218,10 @@ tsdf_status Engine::run(const std::vector<MapRef> &maps, const std::vector<ScanR
 }
 
 tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector<ScanRef> &scans, size_t b,
-                              size_t e, const int32_t lt[3], int32_t tile_grid, tsdf_scan_stats *stats)
+                              size_t e, const LaunchShape &shape, tsdf_scan_stats *stats)
 {
+    const int32_t *lt = shape.lt;
+    const uint32_t bb = (uint32_t)shape.bin_block;
     const size_t nscans = e - b;
     // map slots in order of first appearance, and each scan's sequence slot
     std::vector<int32_t> slot_of(maps.size(), -1), seq(nscans), used;
@@ -268,7 +271,7 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
     for (size_t k = 0; k < nscans; ++k) {
         const ScanRef &s = scans[b + k];
         block0[k] = (uint32_t)nblocks;
-        nblocks += (uint64_t)((s.n + kBinBlock - 1) / kBinBlock);
+        nblocks += (uint64_t)((s.n + bb - 1) / bb);
         npoints += (uint64_t)s.n;
         if (s.host) nhost += (uint64_t)s.n;
     }
@@ -292,7 +295,7 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
                 nc = std::max(need_c, c_cap_ + c_cap_ / 2);
                 ng = std::max(need_g, g_cap_ + g_cap_ / 2);
             }
-            const size_t bytes = up(5 * nc * sizeof(uint32_t)) + 2 * up(ng * sizeof(uint32_t));
+            const size_t bytes = up(5 * nc * sizeof(uint32_t)) + up(ng * sizeof(uint4));
             if (arr_external_) {
                 if (bytes > arr_bytes_) return TSDF_ERANGE;
                 ECHK(hipStreamSynchronize(stream_));
@@ -351,11 +354,13 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
     hdr->nblocks = (uint32_t)nblocks;
     hdr->cap = (uint32_t)std::min<size_t>(entries_cap_ / (2 * sizeof(uint4)), 0xffffffffu);
     hdr->want_stats = stats ? 1u : 0u;
+    hdr->bin_block = bb;
+    hdr->pad = 0;
     memcpy(h + L.maps, md.data(), nmaps * sizeof(MapDev));
     ScanDev *sd = (ScanDev *)(h + L.scans);
     uint32_t *bs = (uint32_t *)(h + L.block_scan);
-    int32_t *ss = (int32_t *)(h + L.seq_scan);
-    for (size_t j = 0; j < (size_t)nmaps * S; ++j) ss[j] = -1;
+    int4 *ss = (int4 *)(h + L.seq_sensor);
+    for (size_t j = 0; j < (size_t)nmaps * S; ++j) ss[j] = make_int4(0, 0, 0, 0);
     for (size_t k = 0; k < nscans; ++k) {
         const ScanRef &s = scans[b + k];
         const MapRef &m = maps[s.map];
@@ -370,27 +375,33 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
         d.seq = seq[k];
         d.block0 = block0[k];
         d.pad = 0;
-        const uint32_t nb = (uint32_t)((s.n + kBinBlock - 1) / kBinBlock);
+        const uint32_t nb = (uint32_t)((s.n + bb - 1) / bb);
         for (uint32_t q = 0; q < nb; ++q) bs[block0[k] + q] = (uint32_t)k;
-        ss[d.map * S + d.seq] = (int32_t)k;
+        ss[d.map * S + d.seq] = make_int4(d.rp.o[0], d.rp.o[1], d.rp.o[2], d.rp.tau);
     }
     LaunchCaps caps;
     caps.blocks = (uint32_t)nblocks;
     caps.gtiles = (uint32_t)gtiles;
     caps.scans = (uint32_t)nscans;
+    caps.bin_block = bb;
+    caps.tile_block = (uint32_t)shape.tile_block;
+    caps.stats = stats ? 1u : 0u;
     {
         // LDS of a tile workgroup: G key buffers (8 bytes per voxel) and the
-        // cached tile (4 bytes per voxel); G as large as ~32 KB allows, so
-        // that the five workgroups a CU holds (the kernel's register budget
-        // allows five waves per SIMD) fit its 160 KB; the persistent grid
-        // fills the CUs
+        // cached tile (4 bytes per voxel); G as large as ~32 KB per 256
+        // threads allows, so that the workgroups a CU holds (the kernel's
+        // register budget allows five waves per SIMD: five workgroups of
+        // 256, two of 512) fit its 160 KB; the persistent grid fills the CUs
         const size_t tvox = (size_t)1 << (lt[0] + lt[1] + lt[2]);
-        const int64_t gfit = ((int64_t)(32 * 1024) / (int64_t)tvox - 4) / 8;
+        const int64_t budget = (int64_t)(32 * 1024) * (shape.tile_block / 256);
+        const int64_t gfit = (budget / (int64_t)tvox - 4) / 8;
         const int32_t G = (int32_t)std::max<int64_t>(1, std::min<int64_t>({gfit, 8, (int64_t)S}));
         hdr->G = G;
         caps.tile_lds = (uint32_t)((8 * (size_t)G + 4) * tvox);
-        const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / caps.tile_lds));
-        caps.tile_grid = tile_grid > 0 ? tile_grid : num_cu_ * per_cu;
+        const int by_waves = 20 / (shape.tile_block / 64);  // five waves per SIMD, four SIMDs
+        const int per_cu =
+            (int)std::max<size_t>(1, std::min<size_t>((size_t)by_waves, (160 * 1024) / caps.tile_lds));
+        caps.tile_grid = shape.tile_grid > 0 ? shape.tile_grid : num_cu_ * per_cu;
     }
     ECHK(hipMemcpyAsync(desc_dev_, h, L.total, hipMemcpyHostToDevice, stream_));
     ECHK(hipEventRecord(desc_ev_[dk], stream_));
@@ -403,15 +414,14 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
     B.maps = (MapDev *)(dd + L.maps);
     B.scans = (ScanDev *)(dd + L.scans);
     B.block_scan = (uint32_t *)(dd + L.block_scan);
-    B.seq_scan = (int32_t *)(dd + L.seq_scan);
+    B.seq_sensor = (int4 *)(dd + L.seq_sensor);
     uint32_t *arr = (uint32_t *)arr_;
     B.counts = arr;
     B.offsets = arr + c_cap_;
     B.cursor = arr + 2 * c_cap_;
     B.tile_vis = arr + 3 * c_cap_;
     B.tile_upd = arr + 4 * c_cap_;
-    B.nonempty = (uint32_t *)((char *)arr_ + up(5 * c_cap_ * 4));
-    B.nonempty_map = (uint32_t *)((char *)B.nonempty + up(g_cap_ * 4));
+    B.jobs = (uint4 *)((char *)arr_ + up(5 * c_cap_ * 4));
     B.entries = (uint4 *)entries_;
     B.entries2 = B.entries + entries_cap_ / (2 * sizeof(uint4));
     B.valid_part = (uint32_t *)valid_;

@@ -16,6 +16,15 @@ struct MapRef {
     hipStream_t stream;
 };
 
+// How a batch is cut up and launched: tiles of 2^lt voxels, tile_grid
+// persistent tile workgroups (0: as many as fit), and the block sizes.
+struct LaunchShape {
+    int32_t lt[3];
+    int32_t tile_grid;
+    int32_t bin_block;   // 128, 256 or 512
+    int32_t tile_block;  // 256 or 512
+};
+
 struct ScanRef {
     int32_t map;  // index into the maps vector
     const float *xyz;
@@ -40,8 +49,8 @@ public:
 
     // Integrate the scans (in order per map). stats: one entry per scan or
     // null. Returns TSDF_EINVAL before doing anything for bad arguments.
-    tsdf_status run(const std::vector<MapRef> &maps, const std::vector<ScanRef> &scans, const int32_t lt[3],
-                    int32_t tile_grid, tsdf_scan_stats *stats);
+    tsdf_status run(const std::vector<MapRef> &maps, const std::vector<ScanRef> &scans, const LaunchShape &shape,
+                    tsdf_scan_stats *stats);
 
     hipStream_t stream() const { return stream_; }
     bool poisoned() const { return poisoned_; }
@@ -57,7 +66,7 @@ public:
 
 private:
     tsdf_status run_chunk(const std::vector<MapRef> &maps, const std::vector<ScanRef> &scans, size_t b, size_t e,
-                          const int32_t lt[3], int32_t tile_grid, tsdf_scan_stats *stats);
+                          const LaunchShape &shape, tsdf_scan_stats *stats);
     tsdf_status grow(void **p, size_t *cap, size_t need, bool zero, bool host_pinned = false);
     tsdf_status fail();
 
@@ -73,7 +82,7 @@ private:
     hipEvent_t desc_ev_[2] = {nullptr, nullptr};
     bool desc_ev_live_[2] = {false, false};
     int desc_cur_ = 0;
-    // tile arrays: counts | offsets | cursor | tile_vis | tile_upd (c_cap each), nonempty (g_cap)
+    // tile arrays: counts | offsets | cursor | tile_vis | tile_upd (c_cap each), jobs (g_cap)
     void *arr_ = nullptr;
     size_t arr_bytes_ = 0;
     bool arr_external_ = false;

@@ -22,7 +22,8 @@ namespace tsdf {
 // submission order.
 // ---------------------------------------------------------------------------
 
-constexpr int kBinBlock = 256;   // binning threads per block (one ray each)
+constexpr int kBinBlock = 256;   // default binning threads per block (one ray each); 128 and 512 also run
+constexpr int kTileBlockDefault = 256;  // default tile workgroup size; 512 also runs
 constexpr int kMaxEmit = 6;      // tiles per ray listed in LDS before taking positions (more go
                                   // straight to their runs)
 constexpr int kHashSlots = 1024; // per-block LDS table that merges (tile, seq) keys
@@ -59,6 +60,8 @@ struct BatchHdr {
     uint32_t nblocks;    // binning blocks of this batch
     uint32_t cap;        // entry capacity
     uint32_t want_stats;
+    uint32_t bin_block;  // binning threads per block (one ray each)
+    uint32_t pad;
 };
 
 constexpr int kQueues = 8;  // tile job queues, one per XCD (workgroup b runs on XCD b % 8)
@@ -80,14 +83,13 @@ struct BatchArrays {
     MapDev *maps;
     ScanDev *scans;
     uint32_t *block_scan;  // [nblocks] scan of each binning block
-    int32_t *seq_scan;     // [nmaps * S] scan of (map, seq), -1 if none
+    int4 *seq_sensor;      // [nmaps * S] sensor position (fixed point) and tau of the scan at (map, seq)
     uint32_t *counts;      // [S * gtiles] entries per (seq, tile), seq-major; zero between batches
     uint32_t *offsets;     // [S * gtiles] start of each run
     uint32_t *cursor;      // [S * gtiles] fill position
     uint32_t *tile_vis;    // [S * gtiles] visits per (seq, tile), when stats are wanted
     uint32_t *tile_upd;    // [S * gtiles] voxels updated per (seq, tile)
-    uint32_t *nonempty;    // [gtiles] tiles with a ray
-    uint32_t *nonempty_map; // [gtiles] map slot of each listed tile
+    uint4 *jobs;           // [gtiles] busy tiles: (global tile, map slot, busy sequence slots as a 64-bit mask)
     uint4 *entries;        // [cap] (point index, q.x, q.y, q.z), by tile then seq
     uint4 *entries2;       // [cap] (r, packed band offsets, crossing counts at tile entry)
     uint32_t *valid_part;  // [nblocks] points with a ray per binning block
@@ -107,7 +109,13 @@ struct LaunchCaps {
     uint32_t scans;       // scans
     int32_t tile_grid;    // tile workgroups
     uint32_t tile_lds;    // dynamic LDS bytes of a tile workgroup
+    uint32_t bin_block;   // binning threads per block: 128, 256 or 512
+    uint32_t tile_block;  // tile workgroup size: 256 or 512
+    uint32_t stats;       // per-scan counts wanted: k_stats runs only then
 };
+
+// The block sizes the kernels are built for.
+bool launch_blocks_ok(int32_t bin_block, int32_t tile_block);
 
 // Events recorded (when non-null) after binning and after the tile pass,
 // for per-stage timing.

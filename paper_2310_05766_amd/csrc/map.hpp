@@ -18,6 +18,8 @@ struct tsdf_map {
     int device = 0;
     int32_t lt[3] = {0, 0, 0};  // integration tiling; {0, 0, 0}: chosen per call
     int32_t tile_grid = 0;      // 0: as many workgroups as fit the device
+    int32_t bin_block = 0;      // binning threads per block; 0: the default
+    int32_t tile_block = 0;     // tile workgroup size; 0: the default
     std::unique_ptr<tsdf::Engine> engine;  // single-scan integration on the map's stream
     // vertical interpolation between scan lines, or free-space carving (their
     // own path through a key volume over the window, interp.hip)
@@ -88,6 +90,19 @@ inline const int32_t *tiling_for(const tsdf_map *m, bool batch)
 {
     if (m->lt[0] != 0) return m->lt;
     return batch ? kBatchTiling : kPlainTiling;
+}
+
+// The launch shape of an integration on this map (a batch takes its first
+// scan's map's).
+inline LaunchShape launch_shape(const tsdf_map *m, bool batch)
+{
+    LaunchShape sh;
+    const int32_t *lt = tiling_for(m, batch);
+    for (int a = 0; a < 3; ++a) sh.lt[a] = lt[a];
+    sh.tile_grid = m->tile_grid;
+    sh.bin_block = m->bin_block > 0 ? m->bin_block : kBinBlock;
+    sh.tile_block = m->tile_block > 0 ? m->tile_block : kTileBlockDefault;
+    return sh;
 }
 
 }  // namespace tsdf

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_noalloc_setup(BatchArrays B, BatchHdr h
         *B.hdr = hdr;
         B.maps[0] = md;
         B.scans[0] = sd;
-        B.seq_scan[0] = 0;
+        B.seq_sensor[0] = make_int4(sd.rp.o[0], sd.rp.o[1], sd.rp.o[2], sd.rp.tau);
     }
     uint32_t *ctl = reinterpret_cast<uint32_t *>(B.ctl);
     for (uint32_t j = t; j < (uint32_t)(sizeof(BatchCtl) / 4); j += stride) ctl[j] = 0;
@@ -89,15 +89,14 @@ size_t noalloc_layout(void *base, uint32_t nblocks, uint32_t gtiles, uint32_t ca
     A.hdr = (BatchHdr *)take(sizeof(BatchHdr));
     A.maps = (MapDev *)take(sizeof(MapDev));
     A.scans = (ScanDev *)take(sizeof(ScanDev));
-    A.seq_scan = (int32_t *)take(sizeof(int32_t));
+    A.seq_sensor = (int4 *)take(sizeof(int4));
     A.block_scan = (uint32_t *)take((size_t)nblocks * 4);
     A.counts = (uint32_t *)take((size_t)gtiles * 4);
     A.offsets = (uint32_t *)take((size_t)gtiles * 4);
     A.cursor = (uint32_t *)take((size_t)gtiles * 4);
     A.tile_vis = (uint32_t *)take((size_t)gtiles * 4);
     A.tile_upd = (uint32_t *)take((size_t)gtiles * 4);
-    A.nonempty = (uint32_t *)take((size_t)gtiles * 4);
-    A.nonempty_map = (uint32_t *)take((size_t)gtiles * 4);
+    A.jobs = (uint4 *)take((size_t)gtiles * sizeof(uint4));
     A.valid_part = (uint32_t *)take((size_t)nblocks * 4);
     A.scan_stats = (uint32_t *)take(4 * 4);
     A.entries = (uint4 *)take((size_t)cap * sizeof(uint4));
@@ -149,7 +148,8 @@ extern "C" tsdf_status tsdf_integrate_scan_noalloc(tsdf_map *m, const float *xyz
     if (m->interp_dq > 0 || m->carve) return TSDF_EINVAL;  // the key-volume paths allocate their volume
 
     // the same tables the batch engine builds for a batch of this one scan
-    const int32_t *lt = tiling_for(m, false);
+    const LaunchShape shape = launch_shape(m, false);
+    const int32_t *lt = shape.lt;
     MapDev md;
     md.sdf = m->sdf;
     md.w = m->w;
@@ -178,7 +178,7 @@ extern "C" tsdf_status tsdf_integrate_scan_noalloc(tsdf_map *m, const float *xyz
     sd.seq = 0;
     sd.block0 = 0;
     sd.pad = 0;
-    const uint64_t nblocks = (uint64_t)((n_points + kBinBlock - 1) / kBinBlock);
+    const uint64_t nblocks = (uint64_t)((n_points + shape.bin_block - 1) / shape.bin_block);
     const uint64_t cap = (uint64_t)n_points * (uint64_t)max_tiles_per_ray(m->d.tau_q10, lt) + 1024;
     if (cap >= ((uint64_t)1 << 32)) return TSDF_ERANGE;
     const size_t need = noalloc_layout(nullptr, (uint32_t)nblocks, md.ntot, (uint32_t)cap, nullptr);
@@ -215,13 +215,20 @@ extern "C" tsdf_status tsdf_integrate_scan_noalloc(tsdf_map *m, const float *xyz
         hdr.nblocks = (uint32_t)nblocks;
         hdr.cap = (uint32_t)cap;
         hdr.want_stats = stats ? 1u : 0u;
+        hdr.bin_block = (uint32_t)shape.bin_block;
+        hdr.pad = 0;
         LaunchCaps caps;
         caps.blocks = (uint32_t)nblocks;
         caps.gtiles = md.ntot;
         caps.scans = 1;
+        caps.bin_block = (uint32_t)shape.bin_block;
+        caps.tile_block = (uint32_t)shape.tile_block;
+        caps.stats = stats ? 1u : 0u;
         const size_t tvox = (size_t)1 << (lt[0] + lt[1] + lt[2]);
         caps.tile_lds = (uint32_t)((8 + 4) * tvox);
-        const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / caps.tile_lds));
+        const int by_waves = 20 / (shape.tile_block / 64);
+        const int per_cu =
+            (int)std::max<size_t>(1, std::min<size_t>((size_t)by_waves, (160 * 1024) / caps.tile_lds));
         caps.tile_grid = m->tile_grid > 0 ? m->tile_grid : g_cu[m->device] * per_cu;
         if (launch_noalloc_setup(B, hdr, md, sd, m->stream) != hipSuccess ||
             launch_batch(B, caps, m->stream, nullptr, nullptr, nullptr) != hipSuccess) {

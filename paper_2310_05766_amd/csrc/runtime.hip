@@ -934,7 +934,7 @@ tsdf_status tsdf_integrate_scan(tsdf_map *m, const float *xyz, int64_t n_points,
     if (keyvol_path(m)) return integrate_interp(m, xyz, n_points, kind == TSDF_PTR_HOST, pose, stats);
     std::vector<MapRef> maps{map_ref(m)};
     std::vector<ScanRef> scans{ScanRef{0, xyz, n_points, kind == TSDF_PTR_HOST, pose}};
-    tsdf_status st = m->engine->run(maps, scans, tiling_for(m, false), m->tile_grid, stats);
+    tsdf_status st = m->engine->run(maps, scans, launch_shape(m, false), stats);
     if (st == TSDF_EDEVICE) m->poisoned = true;
     return st;
 }
@@ -1019,7 +1019,7 @@ tsdf_status tsdf_integrate_batch(const tsdf_scan_desc *scans, int32_t count, tsd
         eng = slot.get();
     }
     const tsdf_map *first = scans[0].map;
-    tsdf_status st = eng->run(maps, refs, tiling_for(first, true), first->tile_grid, stats);
+    tsdf_status st = eng->run(maps, refs, launch_shape(first, true), stats);
     if (st == TSDF_EDEVICE)
         for (int32_t k = 0; k < count; ++k) scans[k].map->poisoned = true;
     return st;
@@ -1412,6 +1412,27 @@ tsdf_status tsdf_map_set_tiling(tsdf_map *m, const int32_t log2_tile[3], int32_t
     if (m->poisoned) return TSDF_EDEVICE;
     for (int a = 0; a < 3; ++a) m->lt[a] = log2_tile[a];
     m->tile_grid = tile_workgroups;
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_map_set_blocks(tsdf_map *m, int32_t bin_block, int32_t tile_block)
+{
+    if (!m) return TSDF_EINVAL;
+    const int32_t bb = bin_block > 0 ? bin_block : kBinBlock;
+    const int32_t tb = tile_block > 0 ? tile_block : kTileBlockDefault;
+    if (bin_block < 0 || tile_block < 0 || !launch_blocks_ok(bb, tb)) return TSDF_EINVAL;
+    Guard g(m);
+    if (!g.ok) return TSDF_EBUSY;
+    m->bin_block = bin_block;
+    m->tile_block = tile_block;
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_map_get_blocks(const tsdf_map *m, int32_t *bin_block, int32_t *tile_block)
+{
+    if (!m || !bin_block || !tile_block) return TSDF_EINVAL;
+    *bin_block = m->bin_block > 0 ? m->bin_block : kBinBlock;
+    *tile_block = m->tile_block > 0 ? m->tile_block : kTileBlockDefault;
     return TSDF_OK;
 }
 

@@ -312,6 +312,16 @@ class TsdfMap:
         lt = (C.c_int32 * 3)(*[int(v) for v in log2_tile])
         check(_abi.lib().tsdf_map_set_tiling(self._h, lt, int(workgroups)), "tsdf_map_set_tiling")
 
+    def set_blocks(self, bin_block: int = 0, tile_block: int = 0):
+        """Binning block size (128, 256, 512) and tile workgroup size (256,
+        512); 0 selects the default. Results do not depend on them."""
+        check(_abi.lib().tsdf_map_set_blocks(self._h, int(bin_block), int(tile_block)), "tsdf_map_set_blocks")
+
+    def get_blocks(self):
+        b, t = C.c_int32(), C.c_int32()
+        check(_abi.lib().tsdf_map_get_blocks(self._h, C.byref(b), C.byref(t)), "tsdf_map_get_blocks")
+        return int(b.value), int(t.value)
+
     def get_tiling(self):
         lt = (C.c_int32 * 3)()
         g = C.c_int32()

@@ -143,6 +143,34 @@ def test_few_tile_workgroups_drain_every_queue(workgroups):
     om.close()
 
 
+@pytest.mark.parametrize("blocks", [(128, 256), (512, 256), (256, 512), (512, 512), (128, 512)])
+def test_every_block_size_gives_the_same_map(blocks):
+    """Binning blocks of 128, 256 and 512 points and tile workgroups of 256
+    and 512 threads: the same map and counts as the oracle, for single
+    scans and for a batch of several scans of one map."""
+    from paper_2310_05766_amd import TsdfError
+    from paper_2310_05766_amd.tsdf import integrate_batch
+    w = synth.config1()
+    spec, sc = w.maps[0], w.scans[0]
+    om = oracle.OracleMap.from_spec(spec)
+    gm = gpu_map(spec.dims, spec.origin, spec.voxel_size, spec.tau_u, spec.w_max)
+    gm.set_blocks(*blocks)
+    assert gm.get_blocks() == tuple(blocks)
+    poses = [sc.pose] + [synth.fuzz_pose((blocks, k), 0.4) for k in range(9)]
+    for p in poses[:2]:
+        assert gm.integrate(sc.xyz, p, stats=True) == om.integrate(sc.xyz, p)
+    st = integrate_batch([(gm, sc.xyz, p) for p in poses[2:]], stats=True)
+    assert st == [om.integrate(sc.xyz, p) for p in poses[2:]]
+    assert same(gm, om, spec.dims)
+    for bad in [(64, 256), (256, 128), (300, 256), (-1, 0)]:
+        with pytest.raises(TsdfError):
+            gm.set_blocks(*bad)
+    gm.set_blocks(0, 0)
+    assert gm.get_blocks() == (256, 256)
+    gm.close()
+    om.close()
+
+
 def test_invalid_tilings_rejected():
     from paper_2310_05766_amd import TsdfError
     gm = gpu_map((32, 32, 32), (-16, -16, -16), 0.05, 3072, 64)
@@ -218,8 +246,12 @@ def test_autotuner_candidates_agree(tmp_path, monkeypatch):
     torch.cuda.synchronize()
     best = autotune(spec, sample, mode="batch", reps=1)
     assert tuple(best["lt"]) in [tuple(c["lt"]) for c in best["candidates"]]
+    # all three knobs were searched and are recorded: tiling, workgroups, block sizes
+    seen = {(c["bin_block"], c["tile_block"]) for c in best["candidates"]}
+    assert {(256, 256), (128, 256), (512, 256), (256, 512), (512, 512)} <= seen
     again = autotune(spec, sample, mode="batch", reps=1)
     assert again["cached"] and tuple(again["lt"]) == tuple(best["lt"])
+    assert (again["bin_block"], again["tile_block"]) == (best["bin_block"], best["tile_block"])
 
 
 @pytest.mark.parametrize("lt", [(2, 2, 5), (3, 3, 6), (4, 4, 4), (0, 0, 0)])
