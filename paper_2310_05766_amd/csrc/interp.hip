@@ -11,9 +11,10 @@
 // one thread walks one ray's band and each band voxel's fill segment and
 // resolves keys with 64-bit atomicMin on a key volume over the window (8
 // bytes per voxel, all EMPTY between scans) and marks the key's run of 64
-// slots as touched (one byte per run, a plain store); a second kernel, one
-// wave per 64 runs, merges the keys of touched runs (Eq. (1), Eq. (2)) and
-// empties them again.
+// slots as touched (one byte per run, a plain store: an atomic that returns
+// the old key, to mark only on the first candidate, is slower); a second
+// kernel, one wave per 64 runs, merges the keys of touched runs (Eq. (1),
+// Eq. (2)) and empties them again.
 //
 // Free-space carving uses the same key volume and merge: a ray longer than
 // tau also walks [o, S] from the sensor to the start of its band (the long
@@ -291,9 +292,12 @@ __global__ __launch_bounds__(kInterpBlock) __attribute__((amdgpu_waves_per_eu(4,
 }
 
 // One wave per group of 64 runs of 64 slots: the wave reads the group's 64
-// touched bytes at once and clears them, then merges the touched runs one
-// after the other, each run's keys read before the previous run is written
-// back (a run's keys, then its voxels: two dependent reads per run).
+// touched bytes at once and clears them, then merges the touched runs
+// kMergeBatch at a time: the batch's keys are all requested together, then
+// the voxels of its touched slots, so that a wave waits on two dependent
+// reads per batch instead of per run.
+constexpr int kMergeBatch = 8;
+
 __global__ __launch_bounds__(256) void k_interp_merge(InterpScan P, int64_t nvox)
 {
     uint64_t updated = 0;
@@ -307,25 +311,38 @@ __global__ __launch_bounds__(256) void k_interp_merge(InterpScan P, int64_t nvox
         const bool t = b0 + lane < nruns && P.touched[b0 + lane] != 0;
         if (t) P.touched[b0 + lane] = 0;
         uint64_t mask = __ballot(t);  // the same for the whole wave
-        if (!mask) continue;
-        int64_t j = (b0 + __builtin_ctzll(mask)) * 64 + lane;
-        unsigned long long key = j < nvox ? P.keys[j] : kEmptyKey;
-        for (;;) {
-            mask &= mask - 1;
-            int64_t jn = 0;
-            unsigned long long keyn = kEmptyKey;
-            if (mask) {
-                jn = (b0 + __builtin_ctzll(mask)) * 64 + lane;
-                if (jn < nvox) keyn = P.keys[jn];
+        while (mask) {
+            int64_t j[kMergeBatch];
+            unsigned long long key[kMergeBatch];
+#pragma unroll
+            for (int b = 0; b < kMergeBatch; ++b) {
+                j[b] = 0;
+                key[b] = kEmptyKey;
+                if (mask) {
+                    j[b] = (b0 + __builtin_ctzll(mask)) * 64 + lane;
+                    mask &= mask - 1;
+                    if (j[b] < nvox) key[b] = P.keys[j[b]];
+                }
             }
-            if (key != kEmptyKey) {
-                merge_key(P.sdf[j], P.w[j], key, P.w_max);
-                P.keys[j] = kEmptyKey;
+            int16_t sv[kMergeBatch], wv[kMergeBatch];
+#pragma unroll
+            for (int b = 0; b < kMergeBatch; ++b) {
+                sv[b] = 0;
+                wv[b] = 0;
+                if (key[b] != kEmptyKey) {
+                    sv[b] = P.sdf[j[b]];
+                    wv[b] = P.w[j[b]];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < kMergeBatch; ++b) {
+                if (key[b] == kEmptyKey) continue;
+                merge_key(sv[b], wv[b], key[b], P.w_max);
+                P.sdf[j[b]] = sv[b];
+                P.w[j[b]] = wv[b];
+                P.keys[j[b]] = kEmptyKey;
                 ++updated;
             }
-            if (!mask) break;
-            j = jn;
-            key = keyn;
         }
     }
     block_add(updated, &P.counters[2]);
