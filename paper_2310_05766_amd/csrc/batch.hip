@@ -21,6 +21,8 @@
 //                 to its first voxel in the tile (exact crossing counts) and
 //                 walks the tile; candidates meet in LDS; then the merge
 //   k_stats       per-scan counts, when asked for
+#include <string.h>
+
 #include "internal.hpp"
 
 namespace tsdf {
@@ -53,8 +55,10 @@ __device__ __forceinline__ uint4 entry_ray(const Ray &R, uint32_t cpack)
     return make_uint4((uint32_t)R.r, o0 | o1 << 16, o2 | (cpack & 0xffffu) << 16, cpack >> 16);
 }
 
-template <bool kFill, int kBinBlock>
-__global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
+// kInline (counting pass only): the batch is one scan whose descriptors are
+// I, not yet in memory.
+template <bool kFill, int kBinBlock, bool kInline>
+__global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B, InlineDesc I)
 {
     __shared__ uint32_t h_key[kHashSlots];  // key + 1; 0 = free
     __shared__ uint32_t h_cnt[kHashSlots];
@@ -63,7 +67,16 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
     __shared__ uint32_t s_slot[kFill ? kMaxEmit * kBinBlock : 1];
     __shared__ uint16_t s_rank[kFill ? kMaxEmit * kBinBlock : 1];
     __shared__ uint32_t s_valid;
-    const BatchHdr H = *B.hdr;
+    // a one-scan batch's descriptors come with the counting launch, which
+    // stores them for the kernels after it
+    constexpr bool inl = !kFill && kInline;
+    const BatchHdr H = inl ? I.hdr : *B.hdr;
+    if (inl && blockIdx.x == 0 && threadIdx.x == 0) {
+        *B.hdr = I.hdr;
+        B.maps[0] = I.map;
+        B.scans[0] = I.scan;
+        B.seq_sensor[0] = make_int4(I.scan.rp.o[0], I.scan.rp.o[1], I.scan.rp.o[2], I.scan.rp.tau);
+    }
     if (!kFill && blockIdx.x == 0 && threadIdx.x == 0) {
         // the allocation counters of the previous batch are done with (the
         // grid always has a block 0, also for a batch without points)
@@ -81,9 +94,11 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B)
     if (threadIdx.x == 0) s_valid = 0;
     __syncthreads();
 
-    const uint32_t s = B.block_scan[blockIdx.x];
-    const ScanDev &SD = B.scans[s];
-    const MapDev &MD = B.maps[SD.map];
+    // (a one-scan batch's block table is written here, for the fill)
+    if (inl && threadIdx.x == 0) B.block_scan[blockIdx.x] = 0u;
+    const uint32_t s = inl ? 0u : B.block_scan[blockIdx.x];
+    const ScanDev &SD = inl ? I.scan : B.scans[s];
+    const MapDev &MD = inl ? I.map : B.maps[SD.map];
     const int64_t i = (int64_t)(blockIdx.x - SD.block0) * kBinBlock + threadIdx.x;
     const RayParams rp = SD.rp;
     Ray R;
@@ -698,17 +713,19 @@ int32_t max_tiles_per_ray(int32_t tau, const int32_t lt[3])
 namespace {
 
 template <int kBB>
-void launch_bin(bool fill, uint32_t bins, const BatchArrays &B, hipStream_t stream)
+void launch_bin(bool fill, uint32_t bins, const BatchArrays &B, const InlineDesc &I, hipStream_t stream)
 {
-    if (fill) hipLaunchKernelGGL((k_bin<true, kBB>), dim3(bins), dim3(kBB), 0, stream, B);
-    else hipLaunchKernelGGL((k_bin<false, kBB>), dim3(bins), dim3(kBB), 0, stream, B);
+    if (fill) hipLaunchKernelGGL((k_bin<true, kBB, false>), dim3(bins), dim3(kBB), 0, stream, B, I);
+    else if (I.on) hipLaunchKernelGGL((k_bin<false, kBB, true>), dim3(bins), dim3(kBB), 0, stream, B, I);
+    else hipLaunchKernelGGL((k_bin<false, kBB, false>), dim3(bins), dim3(kBB), 0, stream, B, I);
 }
 
-void launch_bin_any(bool fill, uint32_t bins, uint32_t block, const BatchArrays &B, hipStream_t stream)
+void launch_bin_any(bool fill, uint32_t bins, uint32_t block, const BatchArrays &B, const InlineDesc &I,
+                    hipStream_t stream)
 {
-    if (block == 128) launch_bin<128>(fill, bins, B, stream);
-    else if (block == 512) launch_bin<512>(fill, bins, B, stream);
-    else launch_bin<256>(fill, bins, B, stream);
+    if (block == 128) launch_bin<128>(fill, bins, B, I, stream);
+    else if (block == 512) launch_bin<512>(fill, bins, B, I, stream);
+    else launch_bin<256>(fill, bins, B, I, stream);
 }
 
 }  // namespace
@@ -719,15 +736,17 @@ bool launch_blocks_ok(int32_t bin_block, int32_t tile_block)
 }
 
 hipError_t launch_batch(const BatchArrays &B, const LaunchCaps &caps, hipStream_t stream, hipEvent_t ev_start,
-                        hipEvent_t ev_binned, hipEvent_t ev_tiles)
+                        hipEvent_t ev_binned, hipEvent_t ev_tiles, const InlineDesc *inl)
 {
     hipError_t e;
     if (ev_start && (e = hipEventRecord(ev_start, stream)) != hipSuccess) return e;
     const uint32_t bins = caps.blocks > 0 ? caps.blocks : 1u;
-    launch_bin_any(false, bins, caps.bin_block, B, stream);
+    InlineDesc none;
+    memset(&none, 0, sizeof(none));
+    launch_bin_any(false, bins, caps.bin_block, B, inl ? *inl : none, stream);
     hipLaunchKernelGGL(k_alloc, dim3((caps.gtiles + kAllocTiles - 1) / kAllocTiles), dim3(kAllocBlock), 0, stream,
                        B);
-    launch_bin_any(true, bins, caps.bin_block, B, stream);
+    launch_bin_any(true, bins, caps.bin_block, B, none, stream);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev_binned && (e = hipEventRecord(ev_binned, stream)) != hipSuccess) return e;
     if (caps.tile_block == 512)

@@ -403,10 +403,23 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
             (int)std::max<size_t>(1, std::min<size_t>((size_t)by_waves, (160 * 1024) / caps.tile_lds));
         caps.tile_grid = shape.tile_grid > 0 ? shape.tile_grid : num_cu_ * per_cu;
     }
-    ECHK(hipMemcpyAsync(desc_dev_, h, L.total, hipMemcpyHostToDevice, stream_));
-    ECHK(hipEventRecord(desc_ev_[dk], stream_));
-    desc_ev_live_[dk] = true;
-    desc_cur_ ^= 1;
+    // a batch of one scan hands its descriptors to the first kernel, which
+    // stores them: no copy and no graph (the arguments change per call);
+    // larger batches copy the tables first
+    const bool one = nscans == 1 && nmaps == 1;
+    InlineDesc I;
+    memset(&I, 0, sizeof(I));
+    if (one) {
+        I.hdr = *hdr;
+        I.map = md[0];
+        I.scan = sd[0];
+        I.on = 1;
+    } else {
+        ECHK(hipMemcpyAsync(desc_dev_, h, L.total, hipMemcpyHostToDevice, stream_));
+        ECHK(hipEventRecord(desc_ev_[dk], stream_));
+        desc_ev_live_[dk] = true;
+        desc_cur_ ^= 1;
+    }
 
     BatchArrays B;
     char *dd = (char *)desc_dev_;
@@ -448,8 +461,8 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
         }
         prof_ev_.push_back({ev[0], ev[1], ev[2], ev[3]});
     }
-    if (prof_on_ || !graphs()) {
-        ECHK(launch_batch(B, caps, stream_, ev[0], ev[1], ev[2]));
+    if (one || prof_on_ || !graphs()) {
+        ECHK(launch_batch(B, caps, stream_, ev[0], ev[1], ev[2], one ? &I : nullptr));
         if (ev[3]) ECHK(hipEventRecord(ev[3], stream_));
     } else {
         // grid sizes rounded up to powers of two, so that few shapes exist

@@ -64,6 +64,18 @@ struct BatchHdr {
     uint32_t pad;
 };
 
+// The descriptors of a batch of one scan, handed to the first binning
+// kernel as arguments: it reads them from there and stores them for the
+// kernels after it, so that no copy precedes the launch (on = 0: the
+// descriptors are in device memory already).
+struct InlineDesc {
+    BatchHdr hdr;
+    MapDev map;
+    ScanDev scan;
+    uint32_t on;
+    uint32_t pad[3];
+};
+
 constexpr int kQueues = 8;  // tile job queues, one per XCD (workgroup b runs on XCD b % 8)
 // Words between two queue counters: each counter on a 128-byte line of its
 // own, so that atomics on different queues do not meet in one line.
@@ -118,9 +130,10 @@ struct LaunchCaps {
 bool launch_blocks_ok(int32_t bin_block, int32_t tile_block);
 
 // Events recorded (when non-null) after binning and after the tile pass,
-// for per-stage timing.
+// for per-stage timing. inl (when non-null, with on = 1): the descriptors of
+// a one-scan batch, stored by the first kernel instead of copied before.
 hipError_t launch_batch(const BatchArrays &B, const LaunchCaps &caps, hipStream_t stream, hipEvent_t ev_start,
-                        hipEvent_t ev_binned, hipEvent_t ev_tiles);
+                        hipEvent_t ev_binned, hipEvent_t ev_tiles, const InlineDesc *inl = nullptr);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
 
 // One scan through the global key volume (interp.hip): with vertical
