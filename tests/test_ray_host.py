@@ -5,6 +5,8 @@ g++ compiles csrc/ray.hpp with its one inline-asm minimum replaced.
   rays with frequent exact ties, at perturbed reciprocal estimates;
 * box_walk_check: the tile pass's resumed box walks against the plain voxel
   walk;
+* rdiv_check: the merge's exact division (Eq. (1)) against exact integer
+  rounding, with perturbed reciprocal estimates;
 * free_walk_check: carving's free-space walk, clipped to random boxes and to
   the carving scan's slabs, against the oracle's segment voxels and keys
   (the oracle is compiled with gcc and linked in)."""
@@ -73,5 +75,13 @@ def test_free_walk_matches_oracle(build, seed):
     together give the segment's voxels in the window."""
     out = subprocess.run([build("free_walk_check", with_oracle=True), str(seed), "3000"], capture_output=True,
                          text=True)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "mismatches 0" in out.stdout
+
+
+def test_merge_divisions_exact(build):
+    """Eq. (1)'s division as the merges run it, exact against integer
+    rounding."""
+    out = subprocess.run([build("rdiv_check"), "5"], capture_output=True, text=True)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "mismatches 0" in out.stdout
