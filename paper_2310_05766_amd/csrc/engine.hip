@@ -96,9 +96,15 @@ Engine::Engine(hipStream_t stream, int device) : stream_(stream), device_(device
         num_cu_ = cu;
     for (int k = 0; k < 2; ++k) {
         if (hipEventCreateWithFlags(&desc_ev_[k], hipEventDisableTiming) != hipSuccess) poisoned_ = true;
+        if (hipEventCreateWithFlags(&desc_used_[k], hipEventDisableTiming) != hipSuccess) poisoned_ = true;
         if (hipEventCreateWithFlags(&pts_ev_[k], hipEventDisableTiming) != hipSuccess) poisoned_ = true;
     }
     if (hipEventCreateWithFlags(&order_ev_, hipEventDisableTiming) != hipSuccess) poisoned_ = true;
+    // (default priority, like every stream of the library)
+    if (hipStreamCreateWithFlags(&copy_stream_, hipStreamNonBlocking) != hipSuccess) {
+        copy_stream_ = nullptr;
+        poisoned_ = true;
+    }
     if (hipMalloc(&ctl_, sizeof(BatchCtl)) != hipSuccess) poisoned_ = true;
     else if (launch_fill_u32((uint32_t *)ctl_, sizeof(BatchCtl) / 4, 0u, stream_) != hipSuccess) poisoned_ = true;
 }
@@ -106,15 +112,22 @@ Engine::Engine(hipStream_t stream, int device) : stream_(stream), device_(device
 Engine::~Engine()
 {
     (void)hipStreamSynchronize(stream_);
+    if (copy_stream_) {
+        (void)hipStreamSynchronize(copy_stream_);
+        (void)hipStreamDestroy(copy_stream_);
+    }
     for (int k = 0; k < 2; ++k) {
         if (desc_host_[k]) (void)hipHostFree(desc_host_[k]);
         if (pts_host_[k]) (void)hipHostFree(pts_host_[k]);
         if (desc_ev_[k]) (void)hipEventDestroy(desc_ev_[k]);
+        if (desc_used_[k]) (void)hipEventDestroy(desc_used_[k]);
+        if (desc_dev_[k]) (void)hipFree(desc_dev_[k]);
+        desc_dev_[k] = nullptr;
         if (pts_ev_[k]) (void)hipEventDestroy(pts_ev_[k]);
     }
     if (order_ev_) (void)hipEventDestroy(order_ev_);
     for (GraphEntry &g : graphs_) (void)hipGraphExecDestroy(g.exec);
-    for (void *p : {desc_dev_, entries_, valid_, stats_, ctl_, pts_dev_})
+    for (void *p : {inline_dev_, entries_, valid_, stats_, ctl_, pts_dev_})
         if (p) (void)hipFree(p);
     if (arr_ && !arr_external_) (void)hipFree(arr_);
     for (auto &t : prof_ev_)
@@ -146,6 +159,7 @@ tsdf_status Engine::grow(void **p, size_t *cap, size_t need, bool zero, bool hos
     size_t ncap = std::max(need, *cap + *cap / 2);
     ncap = up(ncap);
     ECHK(hipStreamSynchronize(stream_));
+    if (copy_stream_) ECHK(hipStreamSynchronize(copy_stream_));
     if (*p) {
         if (host_pinned) ECHK(hipHostFree(*p));
         else ECHK(hipFree(*p));
@@ -283,7 +297,15 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
                  cap_blocks = std::max<size_t>(nblocks, 1);
     const DescLayout L = DescLayout::of(cap_maps, cap_scans, cap_blocks);
     tsdf_status st;
-    if ((st = grow(&desc_dev_, &desc_cap_, L.total, false)) != TSDF_OK) return st;
+    // a batch of one scan hands its descriptors to the first kernel, which
+    // stores them in a table of their own: no copy and no graph (the
+    // arguments change per call); larger batches copy the tables first
+    const bool one = nscans == 1 && nmaps == 1;
+    if (one) {
+        if ((st = grow(&inline_dev_, &inline_cap_, L.total, false)) != TSDF_OK) return st;
+    } else if ((st = grow(&desc_dev_[desc_cur_], &desc_cap_[desc_cur_], L.total, false)) != TSDF_OK) {
+        return st;
+    }
     {
         // tile arrays: counts | offsets | cursor | tile_vis | tile_upd, then
         // the busy-tile list; counts and records are zero between batches,
@@ -403,10 +425,6 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
             (int)std::max<size_t>(1, std::min<size_t>((size_t)by_waves, (160 * 1024) / caps.tile_lds));
         caps.tile_grid = shape.tile_grid > 0 ? shape.tile_grid : num_cu_ * per_cu;
     }
-    // a batch of one scan hands its descriptors to the first kernel, which
-    // stores them: no copy and no graph (the arguments change per call);
-    // larger batches copy the tables first
-    const bool one = nscans == 1 && nmaps == 1;
     InlineDesc I;
     memset(&I, 0, sizeof(I));
     if (one) {
@@ -415,14 +433,18 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
         I.scan = sd[0];
         I.on = 1;
     } else {
-        ECHK(hipMemcpyAsync(desc_dev_, h, L.total, hipMemcpyHostToDevice, stream_));
-        ECHK(hipEventRecord(desc_ev_[dk], stream_));
+        // on the copy stream, after the kernels that last read this device
+        // copy: the copy runs while the previous batch's kernels do, and the
+        // batch's kernels wait only for its end
+        if (desc_used_live_[dk]) ECHK(hipStreamWaitEvent(copy_stream_, desc_used_[dk], 0));
+        ECHK(hipMemcpyAsync(desc_dev_[dk], h, L.total, hipMemcpyHostToDevice, copy_stream_));
+        ECHK(hipEventRecord(desc_ev_[dk], copy_stream_));
         desc_ev_live_[dk] = true;
-        desc_cur_ ^= 1;
+        ECHK(hipStreamWaitEvent(stream_, desc_ev_[dk], 0));
     }
 
     BatchArrays B;
-    char *dd = (char *)desc_dev_;
+    char *dd = (char *)(one ? inline_dev_ : desc_dev_[dk]);
     B.hdr = (BatchHdr *)(dd + L.hdr);
     B.maps = (MapDev *)(dd + L.maps);
     B.scans = (ScanDev *)(dd + L.scans);
@@ -471,6 +493,12 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
         gc.gtiles = pow2_at_least(std::max<uint32_t>(caps.gtiles, 1));
         gc.scans = pow2_at_least(std::max<uint32_t>(caps.scans, 1));
         ECHK(launch(B, gc));
+    }
+    if (!one) {
+        // the next copy into this device table waits for these kernels
+        ECHK(hipEventRecord(desc_used_[dk], stream_));
+        desc_used_live_[dk] = true;
+        desc_cur_ ^= 1;
     }
     // later work on each map's stream waits for this batch
     for (int32_t j = 0; j < nmaps; ++j) {

@@ -74,14 +74,23 @@ private:
     int device_;
     bool poisoned_ = false;
     int num_cu_ = 256;
-    // descriptor tables: device and pinned host copies (double-buffered host side)
-    void *desc_dev_ = nullptr;
-    size_t desc_cap_ = 0;
+    // descriptor tables: pinned host staging and device copies, both
+    // double-buffered; a batch's tables go to the device on copy_stream_,
+    // while the previous batch's kernels still run on stream_
+    void *desc_dev_[2] = {nullptr, nullptr};
+    size_t desc_cap_[2] = {0, 0};
     void *desc_host_[2] = {nullptr, nullptr};
     size_t desc_host_cap_[2] = {0, 0};
-    hipEvent_t desc_ev_[2] = {nullptr, nullptr};
+    hipEvent_t desc_ev_[2] = {nullptr, nullptr};    // staging k copied to device k (copy_stream_)
     bool desc_ev_live_[2] = {false, false};
+    hipEvent_t desc_used_[2] = {nullptr, nullptr};  // kernels reading device k done (stream_)
+    bool desc_used_live_[2] = {false, false};
     int desc_cur_ = 0;
+    hipStream_t copy_stream_ = nullptr;
+    // the tables of one-scan batches, which their first kernel writes (on
+    // stream_ only: no copy, no event)
+    void *inline_dev_ = nullptr;
+    size_t inline_cap_ = 0;
     // tile arrays: counts | offsets | cursor | tile_vis | tile_upd (c_cap each), jobs (g_cap)
     void *arr_ = nullptr;
     size_t arr_bytes_ = 0;

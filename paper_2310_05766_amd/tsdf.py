@@ -29,13 +29,25 @@ def _pose_arg(pose):
     return M, M.ctypes.data_as(C.POINTER(C.c_double))
 
 
+_F32 = None
+
+
+def _torch_float32():
+    global _F32
+    if _F32 is None:
+        import torch
+
+        _F32 = torch.float32
+    return _F32
+
+
 def _points_arg(xyz):
     """(pointer, n, kind, keepalive) for a numpy host array or a torch device tensor."""
     if isinstance(xyz, np.ndarray):
         a = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
         return a.ctypes.data, a.shape[0], _abi.TSDF_PTR_HOST, a
     # torch tensor
-    if str(xyz.dtype) != "torch.float32" or xyz.dim() != 2 or xyz.shape[1] != 3 or not xyz.is_contiguous():
+    if xyz.dtype is not _torch_float32() or xyz.dim() != 2 or xyz.shape[1] != 3 or not xyz.is_contiguous():
         raise ValueError("device points must be a contiguous float32 tensor of shape (n, 3)")
     if not xyz.is_cuda:
         a = xyz.numpy()
@@ -44,6 +56,24 @@ def _points_arg(xyz):
 
 
 _ext_streams = {}
+_order_events = {}
+_recorded = {}  # id(tensor) -> (weak reference, torch streams it was recorded on)
+
+
+def _record_once(t, ts):
+    """t.record_stream(ts), once per tensor and stream: the allocator holds a
+    recorded block until the stream has passed the point where the tensor is
+    freed, which covers every later use on that stream too."""
+    key = id(t)
+    ent = _recorded.get(key)
+    if ent is None or ent[0]() is not t:
+        ent = _recorded[key] = (weakref.ref(t, lambda _r, k=key: _recorded.pop(k, None)), set())
+    sid = ts.cuda_stream
+    if sid not in ent[1]:
+        t.record_stream(ts)
+        ent[1].add(sid)
+
+
 _held_by_stream = {}  # stream handle -> device tensors a caller-given raw stream may still read
 _HOLD_MAX = 64
 
@@ -58,16 +88,25 @@ def _torch_stream(stream):
 def _order_after_torch(handle):
     """The library's stream (handle) waits for torch's current stream, where
     the device points were written: a torch event recorded on the current
-    stream, waited on by the library's stream. No-op for the same stream."""
+    stream, waited on by the library's stream. No-op for the same stream,
+    and when the current stream has finished all its work already."""
     import torch
 
     cur = torch.cuda.current_stream()
     if handle is None or cur.cuda_stream == handle:
         return
+    if cur.query():
+        # everything torch's stream had queued is done, the points included:
+        # nothing to wait for on the device
+        return
     ext = _ext_streams.get(handle)
     if ext is None:
         ext = _ext_streams[handle] = torch.cuda.ExternalStream(handle)
-    ev = torch.cuda.Event()
+    # one event per library stream, recorded again each time: a wait holds
+    # the record it was queued after, so a later record cannot change it
+    ev = _order_events.get(handle)
+    if ev is None:
+        ev = _order_events[handle] = torch.cuda.Event()
     ev.record(cur)
     ext.wait_event(ev)
 
@@ -158,7 +197,7 @@ class TsdfMap:
         _order_after_torch(self._stream)
         if self._tstream is not None:
             for t in tensors:
-                t.record_stream(self._tstream)
+                _record_once(t, self._tstream)
             return
         if len(self._held) >= _HOLD_MAX:
             self.synchronize()
@@ -352,16 +391,16 @@ def integrate_batch(items, stream=None, stats: bool = False):
     after torch's current stream has written them."""
     n = len(items)
     arr = np.zeros(max(n, 1), dtype=_SCAN_DTYPE)
-    keep = []
-    kinds = set()
-    for k, (m, xyz, pose) in enumerate(items):
-        ptr, npts, kind, kp = _points_arg(xyz)
-        keep.append(kp)
-        kinds.add(kind)
-        arr["map"][k] = m.handle
-        arr["xyz"][k] = ptr
-        arr["n"][k] = npts
-        arr["pose"][k] = np.asarray(pose, dtype=np.float64).reshape(16)
+    args = [_points_arg(xyz) for _, xyz, _ in items]
+    keep = [a[3] for a in args]
+    kinds = {a[2] for a in args}
+    if n:
+        # whole columns at once (per-element writes into a structured array
+        # cost more than the launch itself for large batches)
+        arr["map"][:n] = [m.handle for m, _, _ in items]
+        arr["xyz"][:n] = [a[0] for a in args]
+        arr["n"][:n] = [a[1] for a in args]
+        arr["pose"][:n] = np.asarray([np.asarray(p, dtype=np.float64).reshape(16) for _, _, p in items])
     if len(kinds) > 1:
         raise ValueError("a batch takes host points or device points, not both")
     kind = kinds.pop() if kinds else _abi.TSDF_PTR_HOST
@@ -375,7 +414,7 @@ def integrate_batch(items, stream=None, stats: bool = False):
             ts = _torch_stream(stream)
             if ts is not None:
                 for t in tensors:
-                    t.record_stream(ts)
+                    _record_once(t, ts)
             else:
                 _hold_raw(handle, tensors)
     st = (_abi.ScanStats * max(n, 1))() if stats else None
