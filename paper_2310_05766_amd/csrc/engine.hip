@@ -100,11 +100,6 @@ Engine::Engine(hipStream_t stream, int device) : stream_(stream), device_(device
         if (hipEventCreateWithFlags(&pts_ev_[k], hipEventDisableTiming) != hipSuccess) poisoned_ = true;
     }
     if (hipEventCreateWithFlags(&order_ev_, hipEventDisableTiming) != hipSuccess) poisoned_ = true;
-    // (default priority, like every stream of the library)
-    if (hipStreamCreateWithFlags(&copy_stream_, hipStreamNonBlocking) != hipSuccess) {
-        copy_stream_ = nullptr;
-        poisoned_ = true;
-    }
     if (hipMalloc(&ctl_, sizeof(BatchCtl)) != hipSuccess) poisoned_ = true;
     else if (launch_fill_u32((uint32_t *)ctl_, sizeof(BatchCtl) / 4, 0u, stream_) != hipSuccess) poisoned_ = true;
 }
@@ -435,7 +430,15 @@ tsdf_status Engine::run_chunk(const std::vector<MapRef> &maps, const std::vector
     } else {
         // on the copy stream, after the kernels that last read this device
         // copy: the copy runs while the previous batch's kernels do, and the
-        // batch's kernels wait only for its end
+        // batch's kernels wait only for its end. The stream is made for the
+        // first batch of several scans (default priority, like every stream
+        // of the library): engines of one-scan calls hold no extra stream.
+        if (!copy_stream_) {
+            if (hipStreamCreateWithFlags(&copy_stream_, hipStreamNonBlocking) != hipSuccess) {
+                copy_stream_ = nullptr;
+                return fail();
+            }
+        }
         if (desc_used_live_[dk]) ECHK(hipStreamWaitEvent(copy_stream_, desc_used_[dk], 0));
         ECHK(hipMemcpyAsync(desc_dev_[dk], h, L.total, hipMemcpyHostToDevice, copy_stream_));
         ECHK(hipEventRecord(desc_ev_[dk], copy_stream_));
