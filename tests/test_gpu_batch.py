@@ -284,3 +284,36 @@ def test_longest_bands_resume_at_tile_entries(lt):
     assert same(gm, om, dims)
     gm.close()
     om.close()
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_one_scan_and_multi_scan_batches_interleaved_on_one_stream(graphs):
+    """One-scan batches (their descriptors handed to the first kernel, in a
+    table of their own) and batches of several scans (descriptor tables
+    copied on the engine's copy stream, two device copies used in turn)
+    interleaved on one stream, device points, with graph replays and with
+    direct launches: the map equals the oracle's scan by scan."""
+    torch = pytest.importorskip("torch")
+    from paper_2310_05766_amd.tsdf import integrate_batch, set_graph_launch
+    w = synth.config2(12)
+    spec = w.maps[0]
+    say("one-scan and multi-scan batches interleaved, graphs", graphs)
+    om = oracle.OracleMap.from_spec(spec)
+    for s in w.scans:
+        om.integrate(s.xyz, s.pose)
+    dev = [torch.from_numpy(s.xyz).to("cuda") for s in w.scans]
+    st = torch.cuda.Stream()
+    set_graph_launch(graphs)
+    try:
+        from paper_2310_05766_amd.tsdf import TsdfMap
+        gm = TsdfMap.from_spec(spec, stream=st)
+        # sizes 1, 3, 1, 2, 1, 4: every batch kind follows every other
+        k = 0
+        for n in (1, 3, 1, 2, 1, 4):
+            integrate_batch([(gm, dev[j], w.scans[j].pose) for j in range(k, k + n)], stream=st)
+            k += n
+        assert k == len(w.scans)
+        assert same(gm, om, spec.dims)
+        gm.close()
+    finally:
+        set_graph_launch(True)
