@@ -566,11 +566,11 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                 if (!box_walk_resume(q, off, rb.x, c, o, tau, blo, bhi, shb, lds_address(s_keys + (size_t)r * tvox), R,
                                      V))
                     continue;
-                const double taud = (double)tau;
+                const double taud = (double)tau, rh = R.r + 0.5;
                 const uint32_t ihi = i >> 16, ilo = i << 16;
                 uint32_t visits = 0;
                 do {
-                    atomicMin(lds_pointer(V.lv), (unsigned long long)band_key(V.n, R, taud, ihi, ilo));
+                    atomicMin(lds_pointer(V.lv), (unsigned long long)band_key(V.n, rh, R.inv_r2, taud, ihi, ilo));
                     ++visits;
                 } while (box_walk_next(V));
                 if (H.want_stats && visits) atomicAdd(&s_vis[r], visits);

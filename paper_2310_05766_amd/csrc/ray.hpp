@@ -202,18 +202,18 @@ __device__ __forceinline__ double refined_rcp(double d)
 }
 
 // pack_key(voxel_sdf(n, R, tau), i) for a voxel of the band walk, with
-// R.inv_r2 = refined_rcp(2r), taud = tau, ihi = i >> 16 and ilo = i << 16.
-// Such a voxel lies within one voxel diagonal of [S, E], so |q - c| <=
-// tau (1 + 1/r) + 888 (S = o when r <= tau) and x = (2|n| + r) / 2r <
-// 2^17.1. The estimate a * inv_r2 is then off by under 2^-34.8, while a
-// non-integer x lies at least 1 / 2r > 2^-32.8 from the next integer: its
-// floor is floor(x), or x - 1 when x is an integer, and one upward
-// correction makes it exact. No cap is needed: x is far below 2^53 / 2r.
-__device__ __forceinline__ uint64_t band_key(double n, const Ray &R, double taud, uint32_t ihi, uint32_t ilo)
+// rh = r + 1/2, inv_r2 = refined_rcp(2r), taud = tau, ihi = i >> 16 and
+// ilo = i << 16. Such a voxel lies within one voxel diagonal of [S, E], so
+// |q - c| <= tau (1 + 1/r) + 888 (S = o when r <= tau) and x = (2|n| + r) /
+// 2r < 2^17.1. x is a multiple of 1 / 2r, so y = x + 1 / 4r = (2|n| + rh) /
+// 2r has the floor of x and lies at least 1 / 4r > 2^-33.8 (r < 2^31.8) from
+// every integer; its estimate (2|n| + rh) * inv_r2 is off by under 2^-34.8,
+// so the estimate's floor is floor(x) with no correction. The numerator is
+// exact (below 2^51, in halves). No cap is needed: x is far below 2^53 / 2r.
+__device__ __forceinline__ uint64_t band_key(double n, double rh, double inv_r2, double taud, uint32_t ihi,
+                                            uint32_t ilo)
 {
-    const double a = __fma_rn(2.0, fabs(n), R.r);  // exact: below 2^50
-    double k = floor(a * R.inv_r2);
-    k += __fma_rn(k, R.r2, R.r2) <= a ? 1.0 : 0.0;  // (k + 1) 2r <= a
+    const double k = floor(__fma_rn(2.0, fabs(n), rh) * inv_r2);
     const uint32_t as = (uint32_t)min_nonan(k, taud);
     const uint32_t lo = ilo | (n < 0 ? (0x10000u - as) & 0xffffu : as);
     return (uint64_t)(as << 16 | ihi) << 32 | lo;

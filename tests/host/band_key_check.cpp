@@ -1,6 +1,6 @@
 // Host build of the device ray arithmetic (csrc/ray.hpp) checked against
 // exact integer rounding: for the voxels of band walks of random rays, the
-// tile pass's band_key (Newton-refined reciprocal, one upward correction, no
+// tile pass's band_key (Newton-refined reciprocal, a half-unit bias, no
 // cap) and pack_key(voxel_sdf(...)) must both equal
 //   pack_key(sign(n) min(floor((2|n| + r) / 2r), tau), i),  n = (q - c) . D,
 // computed in 128-bit integers. Rays with tiny components make r small, so
@@ -99,7 +99,7 @@ int main(int argc, char **argv)
             int32_t s = (int32_t)(k < P.tau ? k : P.tau);
             if (n < 0) s = -s;
             const uint64_t want = pack_key(s, i);
-            const bool ok_band = (double)n == W.n && band_key(W.n, Rk, (double)P.tau, i >> 16, i << 16) == want;
+            const bool ok_band = (double)n == W.n && band_key(W.n, Rk.r + 0.5, Rk.inv_r2, (double)P.tau, i >> 16, i << 16) == want;
             const bool ok_sdf = fabs(g_pert) > 0x1p-18 || pack_key(voxel_sdf(W.n, R, P.tau), i) == want;
             if (!ok_band || !ok_sdf) {
                 if (bad < 5)
