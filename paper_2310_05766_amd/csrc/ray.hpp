@@ -438,9 +438,9 @@ __device__ __forceinline__ void box_walk_from(const Walk &W, const int32_t lo[3]
         V.dlv[a] = up ? (1 << sh[a]) : -(1 << sh[a]);
         // crossings until the walk leaves the box on this axis (at least one)
         const int32_t k = up ? hi[a] - W.g[a] : W.g[a] - lo[a] + 1;
-        first_exit = fmin(first_exit, V.T[a] + (double)(k - 1) * V.dT[a]);
+        first_exit = min_nonan(first_exit, V.T[a] + (double)(k - 1) * V.dT[a]);  // never NaN
     }
-    V.lim = fmin(2.0 * W.lam, first_exit - 1.0);
+    V.lim = min_nonan(2.0 * W.lam, first_exit - 1.0);
     V.n = W.n;
 }
 
@@ -500,11 +500,11 @@ __device__ __forceinline__ bool box_walk_resume(const int32_t q[3], const int32_
 }
 
 // Advance to the next voxel of the box; false when the walk leaves the box
-// or the segment ends.
+// or the segment ends (the state then holds a step past the end, never used:
+// stepping without a branch costs less than testing first).
 __device__ __forceinline__ bool box_walk_next(BoxWalk &V)
 {
     const double tm = min_nonan(V.T[0], min_nonan(V.T[1], V.T[2]));
-    if (tm > V.lim) return false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         // x + (0 or 1) dx as one fma: exact (the sums are integers below
@@ -515,7 +515,7 @@ __device__ __forceinline__ bool box_walk_next(BoxWalk &V)
         V.n = __fma_rn(ef, V.dn[a], V.n);
         V.lv += e ? V.dlv[a] : 0;
     }
-    return true;
+    return tm <= V.lim;
 }
 
 // ---------------------------------------------------------------------------
