@@ -700,15 +700,8 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
 
 }  // namespace
 
-// A band segment spans at most (3 tau + 2) / 1024 + 2 voxels per axis, so
-// it crosses at most span / T_a + 1 tile faces on axis a.
-int32_t max_tiles_per_ray(int32_t tau, const int32_t lt[3])
-{
-    const int32_t span = (3 * tau + 2) / 1024 + 2;
-    int32_t n = 1;
-    for (int a = 0; a < 3; ++a) n += (span >> lt[a]) + 2;
-    return n;
-}
+// Entries one point can emit: the tiles its band segment's walk visits.
+int32_t max_tiles_per_ray(int32_t tau, const int32_t lt[3]) { return band_tiles_bound(tau, lt); }
 
 namespace {
 

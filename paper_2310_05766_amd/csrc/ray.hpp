@@ -166,6 +166,21 @@ __device__ __forceinline__ bool make_ray(const int32_t q[3], const RayParams &P,
     return true;
 }
 
+// Most cells of 2^lt[a] voxels (tiles) that the walk of one band segment
+// [S, E] visits, for any ray of truncation tau. With |off_a - tau D_a / r|
+// <= 1/2 and r <= |D| < r + 1, |E - S| < 2 tau + 4 in both cases of
+// make_ray: 2|off| < 2 tau (1 + 1/r) + sqrt(3) when r > tau, and |D + off| <
+// (r + 1)(1 + tau / r) + 1 <= 2 tau + 3 when S = o (1 <= r <= tau). So
+// sum_a |L_a| < sqrt(3) (2 tau + 4) < 1774 (2 tau + 4) / 1024. The walk steps
+// at most floor(|L_a| / c_a) + 1 times on axis a (cells of c_a fixed-point
+// units) and visits one cell more than it takes events.
+inline int32_t band_tiles_bound(int32_t tau, const int32_t lt[3])
+{
+    const int64_t len = (1774 * (2 * (int64_t)tau + 4) + 1023) / 1024;  // > sum_a |L_a|
+    const int32_t lmin = lt[0] < lt[1] ? (lt[0] < lt[2] ? lt[0] : lt[2]) : (lt[1] < lt[2] ? lt[1] : lt[2]);
+    return 4 + (int32_t)(len >> (10 + lmin));
+}
+
 // Signed distance of the voxel whose centre gives numerator n = (q - c) . D:
 // clamp(rdiv(n, r), -tau, tau). The quotient floor((2|n| + r) / 2r) is
 // capped at tau + 1, so its estimate from the reciprocal is within one and a

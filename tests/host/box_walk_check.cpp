@@ -6,8 +6,12 @@
 // the tile's box (clipped to the window) and runs the box walk. The voxels it
 // visits, in order, with their box index and distance numerator n, must be
 // exactly the voxels of the plain voxel walk that lie in that box, and every
-// such voxel must be reached from some tile. The test driver defines RAY_HPP
-// (a copy of ray.hpp whose one inline-asm minimum is replaced by a compare).
+// such voxel must be reached from some tile. The walk on the tile grid must
+// visit no more cells than band_tiles_bound allows (the entry buffer is sized
+// by it), also for rays built to be long on the grid: near the sensor (r <=
+// tau, S = o) and along the cube's diagonals. The test driver defines
+// RAY_HPP (a copy of ray.hpp whose one inline-asm minimum is replaced by a
+// compare).
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -40,7 +44,25 @@ int main(int argc, char **argv)
     std::mt19937_64 rng(argc > 1 ? strtoull(argv[1], nullptr, 10) : 11);
     const int iters = argc > 2 ? atoi(argv[2]) : 20000;
     long bad = 0, tiles = 0, visits = 0, rays = 0, resumes = 0, direct = 0;
-    int32_t max_count = 0;
+    int32_t max_count = 0, max_cells = 0, cells_at_bound = 0;
+    // cells of the band walk on a grid of 2^lt voxels against the bound
+    auto check_cells = [&](const Ray &R, int32_t tau, const int32_t lt[3], const int32_t org[3]) {
+        const int32_t lc[3] = {10 + lt[0], 10 + lt[1], 10 + lt[2]};
+        const int32_t base[3] = {1024 * org[0], 1024 * org[1], 1024 * org[2]};
+        Walk T;
+        walk_init_cells(R, T, lc, base);
+        double t_ev = -1.0;
+        int typ = 0;
+        int32_t n = 1;
+        while (walk_next_event(T, t_ev, typ) && n < 1000) ++n;
+        const int32_t bound = band_tiles_bound(tau, lt);
+        max_cells = std::max(max_cells, n);
+        cells_at_bound += n == bound ? 1 : 0;
+        if (n > bound) {
+            if (bad < 5) printf("band walk visits %d cells, bound %d (tau %d, lt %d %d %d)\n", n, bound, tau, lt[0], lt[1], lt[2]);
+            ++bad;
+        }
+    };
     for (int it = 0; it < iters; ++it) {
         RayParams P{};
         const int64_t lim = 1ll << std::uniform_int_distribution<int>(0, 24)(rng);
@@ -71,6 +93,7 @@ int main(int argc, char **argv)
             nt[a] = (dims[a] + (1 << lt[a]) - 1) >> lt[a];
         }
         const int32_t sh[3] = {lt[1] + lt[2], lt[2], 0};
+        check_cells(R, P.tau, lt, org);
         const int32_t lc[3] = {10 + lt[0], 10 + lt[1], 10 + lt[2]};
         const int32_t base[3] = {1024 * org[0], 1024 * org[1], 1024 * org[2]};
         // binning side: the tile walk and the crossing counts at each entry
@@ -180,7 +203,29 @@ int main(int argc, char **argv)
             }
         }
     }
-    printf("rays %ld tiles %ld resumes %ld (direct %ld) visits %ld largest crossing count %d mismatches %ld\n", rays,
-           tiles, resumes, direct, visits, max_count, bad);
+    // rays long on the tile grid: short D (r <= tau, the band from the
+    // sensor), directions near the cube's diagonals, the largest tau, the
+    // smallest tiles, and random sub-tile offsets of the point and the sensor
+    for (int it = 0; it < iters; ++it) {
+        RayParams P{};
+        P.tau = it % 3 == 0 ? 32767 : std::uniform_int_distribution<int>(1, 32767)(rng);
+        const int64_t len = it % 2 ? std::uniform_int_distribution<int64_t>(1, 4)(rng)
+                                   : std::uniform_int_distribution<int64_t>(1, 3 * (int64_t)P.tau)(rng);
+        int32_t q[3], lt[3], org[3];
+        for (int a = 0; a < 3; ++a) {
+            P.o[a] = std::uniform_int_distribution<int32_t>(-(1 << 20), 1 << 20)(rng);
+            const int64_t sgn = rng() & 1 ? 1 : -1;
+            q[a] = (int32_t)(P.o[a] + sgn * (len + std::uniform_int_distribution<int64_t>(-2, 2)(rng)));
+            lt[a] = it % 4 == 0 ? 2 : std::uniform_int_distribution<int>(2, 6)(rng);
+            org[a] = std::uniform_int_distribution<int32_t>(-5000, 5000)(rng);
+        }
+        Ray R;
+        if (!make_ray(q, P, R)) continue;
+        ++rays;
+        check_cells(R, P.tau, lt, org);
+    }
+    printf("rays %ld tiles %ld resumes %ld (direct %ld) visits %ld largest crossing count %d largest band walk %d "
+           "cells (%d at the bound) mismatches %ld\n",
+           rays, tiles, resumes, direct, visits, max_count, max_cells, cells_at_bound, bad);
     return bad != 0 || visits == 0;
 }
