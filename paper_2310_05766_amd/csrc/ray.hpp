@@ -106,17 +106,19 @@ __device__ __forceinline__ double floor_div_exact(double a, double d, double inv
 }
 
 // rdiv(n, d) for 1 <= d <= 2^15 and |n| <= 2^15 d (Eq. (1): n = g w + v,
-// d = w + 1 with |g|, |v| <= tau < 2^15): float64 estimate of
-// floor((2|n| + d) / 2d) from the reciprocal, which is within one of it (the
-// quotient is at most 2^15), then one exact correction each way (every
-// product is an integer below 2^53).
+// d = w + 1 with |g|, |v| <= tau < 2^15), with no correction step. x =
+// (2|n| + d) / 2d is a multiple of 1 / 2d, so y = x + 1 / 4d, the quotient
+// of the numerator plus a half, has the floor of x and lies at least 1 / 4d
+// >= 2^-17 from every integer. y <= 2^15 + 1 and the reciprocal of 2d after
+// one Newton step is off by about the square of the estimate's error (far
+// below 2^-20), so the product is off by far less than 2^-17 and its floor
+// is floor(x). The numerator is exact (below 2^33, in halves).
 __device__ __forceinline__ int32_t rdiv_small(int32_t n, int32_t d)
 {
     const double dd = 2.0 * (double)d;
-    const double a = 2.0 * fabs((double)n) + (double)d;
-    double k = floor(a * approx_rcp(dd));
-    k -= k * dd > a ? 1.0 : 0.0;
-    k += __fma_rn(k, dd, dd) <= a ? 1.0 : 0.0;
+    double y = approx_rcp(dd);
+    y = __fma_rn(y, __fma_rn(-dd, y, 1.0), y);
+    const double k = floor(__fma_rn(2.0, fabs((double)n), (double)d + 0.5) * y);
     return n < 0 ? -(int32_t)k : (int32_t)k;
 }
 

@@ -4,7 +4,8 @@
 // 255) and sampled divisors up to 32768, over numerators that cover every
 // residue class near zero, every tie and near-tie k d / 2 +- 1 across the
 // range, the extremes +-32768 d and random values, with the hardware
-// reciprocal modelled as exact and as off by up to 2^-21 either way. The
+// reciprocal modelled as exact and as off by up to 2^-18 either way (its
+// error is far below 2^-20; the Newton step squares it). The
 // test driver defines RAY_HPP (a copy of ray.hpp whose one inline-asm
 // minimum is replaced by a compare).
 #include <cmath>
@@ -38,8 +39,8 @@ static int64_t exact(int64_t n, int64_t d)
 int main(int argc, char **argv)
 {
     std::mt19937_64 rng(argc > 1 ? strtoull(argv[1], nullptr, 10) : 5);
-    const double perts[5] = {0.0, std::ldexp(1.0, -21), -std::ldexp(1.0, -21), std::ldexp(1.0, -23),
-                             -std::ldexp(1.0, -23)};
+    const double perts[7] = {0.0,  std::ldexp(1.0, -18), -std::ldexp(1.0, -18), std::ldexp(1.0, -20),
+                             -std::ldexp(1.0, -20), std::ldexp(1.0, -23), -std::ldexp(1.0, -23)};
     long checks = 0, bad = 0;
     for (double p : perts) {
         g_pert = p;
