@@ -131,9 +131,11 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
         }
         Walk W;
         walk_init(R, W);
+        const double taud = (double)P.rp.tau, rh = R.r + 0.5;
+        const uint32_t ihi = (uint32_t)i >> 16, ilo = (uint32_t)i << 16;
         do {
-            const int32_t s = voxel_sdf(W.n, R, P.rp.tau);
-            const unsigned long long key = pack_key(s, (uint32_t)i);
+            // a voxel of the band walk: band_key is pack_key(voxel_sdf(...))
+            const unsigned long long key = band_key(W.n, rh, R.inv_r2, taud, ihi, ilo);
             // the fill segment of this band voxel: [c - e, c + e]
             int64_t e[3] = {0, 0, 0};
             if (fills && nv > 0) {

@@ -59,9 +59,22 @@ __device__ __forceinline__ uint64_t isqrt_u64(uint64_t n)
     return r;
 }
 
-// Approximate 1/d (v_rcp_f64). Every quotient below is corrected exactly
-// afterwards, so its accuracy only decides how many correction steps run.
+// Approximate 1/d (v_rcp_f64; relative error far below 2^-20). Quotients
+// below either correct its estimate exactly afterwards or refine the
+// reciprocal by Newton steps first, as their error bounds require.
 __device__ __forceinline__ double approx_rcp(double d) { return __builtin_amdgcn_rcp(d); }
+
+// 1 / d to within a few units of 2^-53: the hardware estimate (relative
+// error far below 2^-20) and two Newton steps, each of which squares the
+// error and adds one rounding.
+__device__ __forceinline__ double refined_rcp(double d)
+{
+    double y = approx_rcp(d);
+    double e = __fma_rn(-d, y, 1.0);
+    y = __fma_rn(y, e, y);
+    e = __fma_rn(-d, y, 1.0);
+    return __fma_rn(y, e, y);
+}
 
 // floor(sqrt(n)) for 0 < n < 3 * 2^62 (|D|^2 of a ray, so the root is below
 // 2^31.8): sqrt(n) estimated as n / sqrt(n) from the hardware reciprocal
@@ -91,20 +104,6 @@ __device__ __forceinline__ double min_nonan(double a, double b)
     return r;
 }
 
-// min(floor(a / d), cap) for exact integers 0 <= a < 2^53, 0 < d < 2^34,
-// cap <= 2^17, from an estimate a * inv_d (inv_d ~ 1/d, relative error far
-// below 2^-17): capped at cap (callers clamp the quotient there anyway), the
-// estimate is within one of the answer, so one exact correction each way
-// gives k d <= a < (k + 1) d or k = cap (every product is an exact integer
-// below 2^53).
-__device__ __forceinline__ double floor_div_exact(double a, double d, double inv_d, double cap)
-{
-    double k = fmin(floor(a * inv_d), cap);
-    k -= k * d > a ? 1.0 : 0.0;
-    k += (k < cap && __fma_rn(k, d, d) <= a) ? 1.0 : 0.0;  // (k + 1) d <= a
-    return k;
-}
-
 // rdiv(n, d) for 1 <= d <= 2^15 and |n| <= 2^15 d (Eq. (1): n = g w + v,
 // d = w + 1 with |g|, |v| <= tau < 2^15), with no correction step. x =
 // (2|n| + d) / 2d is a multiple of 1 / 2d, so y = x + 1 / 4d, the quotient
@@ -122,14 +121,6 @@ __device__ __forceinline__ int32_t rdiv_small(int32_t n, int32_t d)
     return n < 0 ? -(int32_t)k : (int32_t)k;
 }
 
-// Rounded division to nearest, ties away from zero: sign(n) floor((2|n| + d) / 2d).
-__device__ __forceinline__ double rdiv_exact(double n, double d2, double inv_d2, double d, double cap)
-{
-    double a = fabs(n);
-    double k = floor_div_exact(2.0 * a + d, d2, inv_d2, cap);
-    return n < 0 ? -k : k;
-}
-
 // One ray: the scan point, its band [S, E] along the ray, and what the
 // distance of each walked voxel needs.
 struct Ray {
@@ -140,7 +131,12 @@ struct Ray {
 };
 
 // D = q - o, r = isqrt(|D|^2); off = rdiv(tau D, r); E = q + off;
-// S = q - off, or S = o when r <= tau. false for D = 0.
+// S = q - off, or S = o when r <= tau. false for D = 0. The division takes
+// no correction step: x = (2|tau D_a| + r) / 2r < 2 tau + 1 < 2^16 is a
+// multiple of 1 / 2r, so with half a unit more on the numerator (exact,
+// below 2^48) the quotient keeps the floor of x and lies at least 1 / 4r >
+// 2^-33.8 from every integer, while its estimate from inv_r2 =
+// refined_rcp(2r) is off by under 2^-35.
 __device__ __forceinline__ bool make_ray(const int32_t q[3], const RayParams &P, Ray &R)
 {
     uint64_t dd = 0;
@@ -155,13 +151,13 @@ __device__ __forceinline__ bool make_ray(const int32_t q[3], const RayParams &P,
     const uint32_t r = isqrt_ray(dd);
     R.r = (double)r;
     R.r2 = 2.0 * R.r;
-    R.inv_r2 = approx_rcp(R.r2);
-    const double tau = (double)P.tau;
+    R.inv_r2 = refined_rcp(R.r2);
+    const double tau = (double)P.tau, rh = R.r + 0.5;
     const bool near = (double)r <= tau;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double off = rdiv_exact(tau * R.D[a], R.r2, R.inv_r2, R.r, 4.0 * tau + 4.0);
-        int32_t oi = (int32_t)off;
+        const int32_t k = (int32_t)floor(__fma_rn(2.0, fabs(tau * R.D[a]), rh) * R.inv_r2);
+        const int32_t oi = R.D[a] < 0 ? -k : k;
         R.E[a] = q[a] + oi;
         R.S[a] = near ? P.o[a] : q[a] - oi;
     }
@@ -204,18 +200,6 @@ __device__ __forceinline__ uint64_t pack_key(int32_t s, uint32_t i)
 {
     uint32_t as = (uint32_t)(s < 0 ? -s : s);
     return ((uint64_t)as << 48) | ((uint64_t)i << 16) | (uint64_t)(uint16_t)(int16_t)s;
-}
-
-// 1 / d to within a few units of 2^-53: the hardware estimate (relative
-// error far below 2^-20) and two Newton steps, each of which squares the
-// error and adds one rounding.
-__device__ __forceinline__ double refined_rcp(double d)
-{
-    double y = approx_rcp(d);
-    double e = __fma_rn(-d, y, 1.0);
-    y = __fma_rn(y, e, y);
-    e = __fma_rn(-d, y, 1.0);
-    return __fma_rn(y, e, y);
 }
 
 // pack_key(voxel_sdf(n, R, tau), i) for a voxel of the band walk, with

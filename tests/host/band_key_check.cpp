@@ -1,14 +1,15 @@
 // Host build of the device ray arithmetic (csrc/ray.hpp) checked against
-// exact integer rounding: for the voxels of band walks of random rays, the
-// tile pass's band_key (Newton-refined reciprocal, a half-unit bias, no
-// cap) and pack_key(voxel_sdf(...)) must both equal
+// exact integer rounding: the ray itself (r, and S, E from the band offsets
+// rdiv(tau D, r)), and for the voxels of band walks of random rays the tile
+// pass's band_key (Newton-refined reciprocal, a half-unit bias, no cap) and
+// pack_key(voxel_sdf(...)) must both equal
 //   pack_key(sign(n) min(floor((2|n| + r) / 2r), tau), i),  n = (q - c) . D,
 // computed in 128-bit integers. Rays with tiny components make r small, so
 // exact ties (2|n| + r divisible by 2r) are frequent. The hardware
-// reciprocal estimate is replaced by 1/d scaled by (1 + p); p runs over
-// errors up to 2^-14 for band_key, whose Newton steps absorb them, and up to
-// 2^-20 for voxel_sdf. The test driver defines RAY_HPP (a copy of ray.hpp
-// whose one inline-asm minimum is replaced by a compare).
+// reciprocal estimate is replaced by 1/d scaled by (1 + p), p running over
+// errors up to 2^-14, which the Newton steps absorb. The test driver defines
+// RAY_HPP (a copy of ray.hpp whose one inline-asm minimum is replaced by a
+// compare).
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -57,8 +58,7 @@ int main(int argc, char **argv)
         ++rays;
         // the ray itself against exact integers: r = floor(sqrt(|D|^2)),
         // off = rdiv(tau D, r), E = q + off, S = q - off (S = o for r <= tau)
-        // (for reciprocal errors within what make_ray's divisions assume)
-        if (fabs(g_pert) <= 0x1p-20) {
+        {
             unsigned __int128 dd = 0;
             __int128 D[3];
             for (int a = 0; a < 3; ++a) {
@@ -82,8 +82,6 @@ int main(int argc, char **argv)
                 ++bad;
             }
         }
-        Ray Rk = R;
-        Rk.inv_r2 = refined_rcp(Rk.r2);
         const uint32_t i = (uint32_t)rng();
         Walk W;
         walk_init(R, W);
@@ -99,8 +97,8 @@ int main(int argc, char **argv)
             int32_t s = (int32_t)(k < P.tau ? k : P.tau);
             if (n < 0) s = -s;
             const uint64_t want = pack_key(s, i);
-            const bool ok_band = (double)n == W.n && band_key(W.n, Rk.r + 0.5, Rk.inv_r2, (double)P.tau, i >> 16, i << 16) == want;
-            const bool ok_sdf = fabs(g_pert) > 0x1p-18 || pack_key(voxel_sdf(W.n, R, P.tau), i) == want;
+            const bool ok_band = (double)n == W.n && band_key(W.n, R.r + 0.5, R.inv_r2, (double)P.tau, i >> 16, i << 16) == want;
+            const bool ok_sdf = pack_key(voxel_sdf(W.n, R, P.tau), i) == want;
             if (!ok_band || !ok_sdf) {
                 if (bad < 5)
                     printf("mismatch: r=%llu tau=%d n=%.17g perturbation %g\n", (unsigned long long)(uint64_t)R.r,
