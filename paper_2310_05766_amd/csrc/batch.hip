@@ -324,13 +324,21 @@ __global__ __launch_bounds__(kAllocBlock) void k_alloc(BatchArrays B)
     }
 }
 
-// Eq. (1) with one unit of weight, Eq. (2).
-__device__ __forceinline__ void merge_one(int16_t &sdf, int16_t &w, uint64_t key, int32_t w_max)
+// Eq. (1) with one unit of weight, Eq. (2), on a voxel state held in 32-bit
+// registers (the stored int16 values, sign-extended once).
+__device__ __forceinline__ void merge_one(int32_t &sdf, int32_t &w, uint64_t key, int32_t w_max)
 {
     const int32_t v = (int16_t)(uint16_t)(key & 0xffffu);
-    const int32_t gw = w, gv = sdf;
-    sdf = (int16_t)rdiv_small(gv * gw + v, gw + 1);
-    w = (int16_t)(gw + 1 < w_max ? gw + 1 : w_max);
+    sdf = rdiv_small(__mul24(sdf, w) + v, w + 1);  // |sdf|, w < 2^15: a 24-bit product
+    w = w + 1 < w_max ? w + 1 : w_max;
+}
+
+__device__ __forceinline__ void merge_one(int16_t &sdf, int16_t &w, uint64_t key, int32_t w_max)
+{
+    int32_t s = sdf, ww = w;
+    merge_one(s, ww, key, w_max);
+    sdf = (int16_t)s;
+    w = (int16_t)ww;
 }
 
 constexpr int kMaxGroup = 8;
@@ -583,7 +591,7 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
 #pragma unroll
                 for (int r = 0; r < kMaxGroup; ++r) upd[r] = 0;
                 for (uint32_t v = threadIdx.x; v < tvox; v += kTileBlock) {
-                    int16_t vs = 0, vw = 0;
+                    int32_t vs = 0, vw = 0;
                     bool touched = false;
 #pragma unroll
                     for (int r = 0; r < kMaxGroup; ++r) {
@@ -601,8 +609,8 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                         ++upd[r];
                     }
                     if (touched) {
-                        c_sdf[v] = vs;
-                        c_w[v] = vw;
+                        c_sdf[v] = (int16_t)vs;
+                        c_w[v] = (int16_t)vw;
                     }
                 }
                 if (H.want_stats)

@@ -105,20 +105,22 @@ __device__ __forceinline__ double min_nonan(double a, double b)
 }
 
 // rdiv(n, d) for 1 <= d <= 2^15 and |n| <= 2^15 d (Eq. (1): n = g w + v,
-// d = w + 1 with |g|, |v| <= tau < 2^15), with no correction step. x =
-// (2|n| + d) / 2d is a multiple of 1 / 2d, so y = x + 1 / 4d, the quotient
-// of the numerator plus a half, has the floor of x and lies at least 1 / 4d
-// >= 2^-17 from every integer. y <= 2^15 + 1 and the reciprocal of 2d after
-// one Newton step is off by about the square of the estimate's error (far
-// below 2^-20), so the product is off by far less than 2^-17 and its floor
-// is floor(x). The numerator is exact (below 2^33, in halves).
+// d = w + 1 with |g|, |v| <= tau < 2^15), with no correction step and no
+// branch on the sign. x = (2|n| + d) / 2d is a multiple of 1 / 2d, so y =
+// x + 1 / 4d, the quotient of the numerator plus a half, has the floor of x
+// and lies at least 1 / 4d >= 2^-17 from every integer. y <= 2^15 + 1 and
+// the reciprocal of 2d after one Newton step is off by about the square of
+// the estimate's error (far below 2^-20), so the product is off by far less
+// than 2^-17. Taken with the sign of n, (2n + sign(n) (d + 1/2)) / 2d =
+// sign(n) y, and truncation towards zero gives sign(n) floor(x). The
+// numerator is exact (below 2^33, in halves).
 __device__ __forceinline__ int32_t rdiv_small(int32_t n, int32_t d)
 {
     const double dd = 2.0 * (double)d;
     double y = approx_rcp(dd);
     y = __fma_rn(y, __fma_rn(-dd, y, 1.0), y);
-    const double k = floor(__fma_rn(2.0, fabs((double)n), (double)d + 0.5) * y);
-    return n < 0 ? -(int32_t)k : (int32_t)k;
+    const double nn = (double)n;
+    return (int32_t)(__fma_rn(2.0, nn, copysign((double)d + 0.5, nn)) * y);
 }
 
 // One ray: the scan point, its band [S, E] along the ray, and what the
