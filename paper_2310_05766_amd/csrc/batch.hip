@@ -39,9 +39,10 @@ __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
 typedef __attribute__((address_space(1))) int16_t glob_i16;
 __device__ __forceinline__ glob_i16 *glob(int16_t *p) { return (glob_i16 *)p; }
 
+template <int kLog2>
 __device__ __forceinline__ uint32_t hash_slot(uint32_t key)
 {
-    return (key * 2654435761u) >> (32 - 10);  // kHashSlots = 2^10
+    return (key * 2654435761u) >> (32 - kLog2);
 }
 
 // Second half of an entry record: what the tile pass needs of the ray
@@ -60,6 +61,13 @@ __device__ __forceinline__ uint4 entry_ray(const Ray &R, uint32_t cpack)
 template <bool kFill, int kBinBlock, bool kInline>
 __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B, InlineDesc I)
 {
+    // the block's (sequence slot, tile) keys: a hash table of two slots per
+    // point of the block (a block of 256 OS1-128 points meets about 100
+    // tiles), so that clearing and flushing it stays cheap; keys that find it
+    // full go straight to their runs
+    constexpr int kHashLog2 = kBinBlock == 128 ? 8 : (kBinBlock == 256 ? 9 : 10);
+    constexpr uint32_t kHashSlots = 1u << kHashLog2;
+    static_assert(kHashSlots == 2 * kBinBlock && kHashSlots <= 1024, "slots fit the 10-bit field below");
     __shared__ uint32_t h_key[kHashSlots];  // key + 1; 0 = free
     __shared__ uint32_t h_cnt[kHashSlots];
     __shared__ uint32_t h_base[kFill ? kHashSlots : 1];
@@ -125,14 +133,15 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B, InlineDesc I)
     const uint32_t nt1 = (uint32_t)__builtin_amdgcn_readfirstlane(MD.nt[1]);
     const uint32_t nt2 = (uint32_t)__builtin_amdgcn_readfirstlane(MD.nt[2]);
     int ne = 0;
+    uint32_t listed = 0;  // fill: bit k set when entry k was listed in LDS (not sent straight to its run)
     double t_in = -1.0;  // event that entered the current tile (none for the first)
     int typ_in = 0;
     while (active) {
         if ((uint32_t)W.g[0] < nt0 && (uint32_t)W.g[1] < nt1 && (uint32_t)W.g[2] < nt2) {
             const uint32_t key =
                 key0 + ((uint32_t)W.g[0] * nt1 + (uint32_t)W.g[1]) * nt2 + (uint32_t)W.g[2];
-            uint32_t h = hash_slot(key), slot = 0xffffu;
-            for (int probe = 0; probe < kHashSlots; ++probe) {
+            uint32_t h = hash_slot<kHashLog2>(key), slot = 0xffffu;
+            for (uint32_t probe = 0; probe < kHashSlots; ++probe) {
                 const uint32_t old = atomicCAS(&h_key[h], 0u, key + 1u);
                 if (old == 0u || old == key + 1u) {
                     slot = h;
@@ -154,6 +163,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B, InlineDesc I)
                 if (kFill) {
                     s_slot[ne * kBinBlock + threadIdx.x] = slot | counts_8to7(cpack) << 10;
                     s_rank[ne * kBinBlock + threadIdx.x] = (uint16_t)rank;
+                    listed |= 1u << ne;
                 }
             } else if (kFill) {  // table full or very long band: straight to the tile's run
                 const uint32_t pos = atomicAdd(&B.cursor[key], 1u);
@@ -188,8 +198,11 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(BatchArrays B, InlineDesc I)
     // each record carries the point's fixed-point position, so the tile pass
     // needs neither the point nor the pose again
     const uint4 rec = make_uint4((uint32_t)i, (uint32_t)q[0], (uint32_t)q[1], (uint32_t)q[2]);
+    // the entries listed in LDS: an entry that found the table full went
+    // straight to its run and left its LDS place unwritten
     const int nl = ne < kMaxEmit ? ne : kMaxEmit;
     for (int k = 0; k < nl; ++k) {
+        if (!((listed >> k) & 1u)) continue;
         const uint32_t sc = s_slot[k * kBinBlock + threadIdx.x];
         const uint32_t pos = h_base[sc & 1023u] + s_rank[k * kBinBlock + threadIdx.x];
         if (pos < H.cap) {

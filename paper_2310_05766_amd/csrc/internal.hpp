@@ -26,7 +26,6 @@ constexpr int kBinBlock = 256;   // default binning threads per block (one ray e
 constexpr int kTileBlockDefault = 256;  // default tile workgroup size; 512 also runs
 constexpr int kMaxEmit = 6;      // tiles per ray listed in LDS before taking positions (more go
                                   // straight to their runs)
-constexpr int kHashSlots = 1024; // per-block LDS table that merges (tile, seq) keys
 constexpr int32_t kMaxTileGrid = 65536;
 constexpr int32_t kMaxSeq = 64;  // scans of one map in one batch
 

@@ -286,6 +286,36 @@ def test_longest_bands_resume_at_tile_entries(lt):
     om.close()
 
 
+@pytest.mark.parametrize("bin_block", [128, 256, 512])
+def test_full_binning_table_sends_entries_straight_to_runs(bin_block):
+    """Points scattered over a wide window with the longest band (tau =
+    32767): each ray crosses about ten tiles, so a binning block meets far
+    more (sequence slot, tile) keys than its hash table holds (two slots per
+    point) and more tiles per point than it lists in LDS; those entries go
+    straight to their runs. Bit-exact with the oracle, one scan and a batch."""
+    from paper_2310_05766_amd.tsdf import integrate_batch
+    vs, tau = 0.1, 32767
+    dims, origin = (256, 256, 64), (-128, -128, -32)
+    rng = np.random.default_rng(bin_block)
+    xyz = rng.uniform([-12.0, -12.0, -3.0], [12.0, 12.0, 3.0], size=(3000, 3)).astype(np.float32)
+    poses = []
+    for j in range(3):
+        p = np.eye(4)
+        p[:3, 3] = [0.03 + 0.4 * j, -0.02 - 0.3 * j, 0.01 + 0.1 * j]
+        poses.append(p)
+    om = oracle.OracleMap(dims, origin, vs, tau, 64)
+    gm = gpu_map(dims, origin, vs, tau, 64)
+    gm.set_blocks(bin_block, 0)
+    say(f"bin block {bin_block}: one scan")
+    assert gm.integrate(xyz, poses[0], stats=True) == om.integrate(xyz, poses[0])
+    say(f"bin block {bin_block}: batch of two")
+    st = integrate_batch([(gm, xyz, p) for p in poses[1:]], stats=True)
+    assert st == [om.integrate(xyz, p) for p in poses[1:]]
+    assert same(gm, om, dims)
+    gm.close()
+    om.close()
+
+
 @pytest.mark.parametrize("graphs", [True, False])
 def test_one_scan_and_multi_scan_batches_interleaved_on_one_stream(graphs):
     """One-scan batches (their descriptors handed to the first kernel, in a
