@@ -29,7 +29,7 @@ namespace tsdf {
 
 namespace {
 
-constexpr int kAllocBlock = 1024;
+constexpr int kAllocBlock = 512;
 
 __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
 
