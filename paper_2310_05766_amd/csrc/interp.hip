@@ -45,8 +45,9 @@ constexpr int kCarveChunkLog2 = 3;
 // from zero, for a divisor 0 < d < 2^32 fixed per ray (given as 2d and
 // 1 / 2d correctly rounded) and |n| < 2^61 with a quotient below 2^31: the
 // float64 estimate is within one of the quotient, and one exact 64-bit
-// correction each way fixes it (no integer division). Here: d = r < 2^30
-// with n = 1024 D_a or (c - o) . D, and d = |int| < 2^31 with n = h int_a.
+// correction each way fixes it (no integer division). Here, once per ray:
+// d = r < 2^30 with n = 1024 D_a (the fills of each band voxel take the
+// float64 forms band_len and fill_offset).
 __device__ __forceinline__ int64_t rdiv_by(int64_t n, uint64_t d2, double inv_d2)
 {
     const uint64_t a = (uint64_t)(n < 0 ? -n : n);
@@ -55,14 +56,6 @@ __device__ __forceinline__ int64_t rdiv_by(int64_t n, uint64_t d2, double inv_d2
     k -= k * d2 > num ? 1u : 0u;
     k += (k + 1) * d2 <= num ? 1u : 0u;
     return n < 0 ? -(int64_t)k : (int64_t)k;
-}
-
-// rdiv(n, 2^20) for |n| < 2^62: a shift.
-__device__ __forceinline__ int64_t rdiv_2p20(int64_t n)
-{
-    const uint64_t a = (uint64_t)(n < 0 ? -n : n);
-    const int64_t k = (int64_t)((2 * a + (1u << 20)) >> 21);
-    return n < 0 ? -k : k;
 }
 
 // Slot of a voxel inside the window: floor_mod(g_a, dims_a) per axis, z
@@ -107,6 +100,7 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
         valid = 1;
         const int64_t rr = (int64_t)R.r;
         int64_t Di[3], v[3] = {0, 0, 0}, nv = 0, dd = 0;
+        double vd[3] = {0.0, 0.0, 0.0}, nvh = 0.0, tt = 0.0;
         for (int a = 0; a < 3; ++a) Di[a] = (int64_t)R.D[a];
         const bool fills = P.dq > 0 && rr < ((int64_t)1 << 30);
         const uint64_t r2 = 2 * (uint64_t)rr;
@@ -128,6 +122,9 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
             nv = (int64_t)isqrt_u64((uint64_t)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
             nv2 = 2 * (uint64_t)nv;
             inv_nv2 = nv > 0 ? 1.0 / (double)nv2 : 0.0;
+            for (int a = 0; a < 3; ++a) vd[a] = (double)v[a];
+            nvh = (double)nv + 0.5;
+            tt = (double)(dd - rr * rr);  // |D|^2 - r^2, in [0, 2r]
         }
         Walk W;
         walk_init(R, W);
@@ -139,12 +136,13 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_scan(InterpScan P)
             // the fill segment of this band voxel: [c - e, c + e]
             int64_t e[3] = {0, 0, 0};
             if (fills && nv > 0) {
-                // (c - o) . D = (q - o) . D - (q - c) . D, the walk's n
-                const int64_t len = rdiv_by(dd - (int64_t)W.n, r2, inv_r2);
-                if (len > 0) {
-                    int64_t h = rdiv_2p20(P.dq * len);
-                    h = h < 65535 ? h : 65535;
-                    for (int a = 0; a < 3; ++a) e[a] = rdiv_by(h * v[a], nv2, inv_nv2);
+                // len = rdiv((c - o) . D, r), (c - o) . D = |D|^2 - n
+                const double len = band_len(W.n, tt, R);
+                if (len > 0.0) {
+                    // h = rdiv(dq len, 2^20): dq len < 2^51 is exact, the
+                    // scaling by 2^-20 too
+                    const double h = fmin(floor(__fma_rn((double)P.dq, len, 524288.0) * 0x1p-20), 65535.0);
+                    for (int a = 0; a < 3; ++a) e[a] = fill_offset(h * vd[a], nvh, inv_nv2);
                 }
             }
             Ray F;  // a segment only: the fill walk needs no distances

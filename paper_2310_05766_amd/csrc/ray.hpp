@@ -222,6 +222,34 @@ __device__ __forceinline__ uint64_t band_key(double n, double rh, double inv_r2,
     return (uint64_t)(as << 16 | ihi) << 32 | lo;
 }
 
+// Vertical interpolation (Sec. VI, Eq. (3)/(4)) of a band voxel c, in
+// float64 with no 64-bit integer product or correction step.
+//
+// len = rdiv((c - o) . D, r) when it is positive (otherwise a value <= 0,
+// which takes no fill), from n = (q - c) . D and t = |D|^2 - r^2 (0 <= t <=
+// 2r), for r < 2^30: (c - o) . D = r^2 + t - n, and for a positive numerator
+// the rounding is floor(x + 1/2), so len = r + floor((2 (t - n) + r) / 2r).
+// That quotient is a multiple of 1 / 2r and below 2^17.2 in magnitude (|q -
+// c| < 2 tau + 2^11 < 2^16.1 and |D| < 2r), and the numerator with half a
+// unit more is exact (below 2^48); its estimate from inv_r2 =
+// refined_rcp(2r) is off by under 2^-33.5 and keeps the floor, which lies at
+// least 1 / 4r > 2^-32 away.
+__device__ __forceinline__ double band_len(double n, double t, const Ray &R)
+{
+    return R.r + floor(__fma_rn(2.0, t - n, R.r + 0.5) * R.inv_r2);
+}
+
+// e_a = rdiv(h v_a, |int|) for 0 <= h <= 65535 and |v_a| <= nv = |int| <
+// 2^31 (so |e_a| <= h): hv = h v_a is exact (below 2^47), nvh = nv + 1/2 and
+// inv_2nv the correctly rounded 1 / 2nv. The quotient with half a unit more
+// on the numerator lies at least 1 / 4nv > 2^-33 from every integer, and its
+// estimate (below 2^16) is off by under 2^-36.
+__device__ __forceinline__ int32_t fill_offset(double hv, double nvh, double inv_2nv)
+{
+    const int32_t k = (int32_t)floor(__fma_rn(2.0, fabs(hv), nvh) * inv_2nv);
+    return hv < 0 ? -k : k;
+}
+
 // Exact walk over the cells { floor((P(t) - base) / cell) : t in [0, 1] },
 // P(t) = S + t (E - S), with cell = 2^lc per axis in fixed point (lc = 10:
 // voxels; 10 + log2(tile edge): tiles). Axis crossings are ordered by their

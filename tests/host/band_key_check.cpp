@@ -7,9 +7,12 @@
 // computed in 128-bit integers. Rays with tiny components make r small, so
 // exact ties (2|n| + r divisible by 2r) are frequent. The hardware
 // reciprocal estimate is replaced by 1/d scaled by (1 + p), p running over
-// errors up to 2^-14, which the Newton steps absorb. The test driver defines
-// RAY_HPP (a copy of ray.hpp whose one inline-asm minimum is replaced by a
-// compare).
+// errors up to 2^-14, which the Newton steps absorb. The interpolation's
+// float64 forms are checked the same way: band_len against rdiv((c - o) .
+// D, r) at every band voxel of rays with r < 2^30, and fill_offset against
+// rdiv(h v_a, nv) for random and tiny (tie-prone) vectors v. The test
+// driver defines RAY_HPP (a copy of ray.hpp whose one inline-asm minimum is
+// replaced by a compare).
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -37,7 +40,7 @@ int main(int argc, char **argv)
     const int iters = argc > 2 ? atoi(argv[2]) : 20000;
     const double perts[] = {0.0, 0x1p-20, -0x1p-20, 0x1p-14, -0x1p-14, 0x1p-30, -0x1p-45};
     const double rsq_perts[] = {0.0, 0x1p-18, -0x1p-18, 0x1p-22, -0x1p-22};
-    long bad = 0, vox = 0, ties = 0, rays = 0;
+    long bad = 0, vox = 0, ties = 0, rays = 0, lens_checked = 0;
     for (int it = 0; it < iters; ++it) {
         g_pert = perts[it % 7];
         g_rsq_pert = rsq_perts[it % 5];
@@ -85,7 +88,25 @@ int main(int argc, char **argv)
         const uint32_t i = (uint32_t)rng();
         Walk W;
         walk_init(R, W);
+        const bool lens = R.r < 1073741824.0;  // band_len's range: r < 2^30
+        __int128 dd2 = 0;
+        for (int a = 0; a < 3; ++a) dd2 += (__int128)((int64_t)q[a] - P.o[a]) * ((int64_t)q[a] - P.o[a]);
+        const double tt = (double)(dd2 - (__int128)(uint64_t)R.r * (__int128)(uint64_t)R.r);
         do {
+            if (lens) {
+                // (c - o) . D and its rounded quotient by r, when positive
+                __int128 N = 0;
+                for (int a = 0; a < 3; ++a)
+                    N += (__int128)(1024 * (int64_t)W.g[a] + 512 - P.o[a]) * ((int64_t)q[a] - P.o[a]);
+                const __int128 rr = (__int128)(uint64_t)R.r;
+                const double got = band_len(W.n, tt, R);
+                const bool ok = N > 0 ? got == (double)((2 * N + rr) / (2 * rr)) : got <= 0.0;
+                if (!ok) {
+                    if (bad < 5) printf("band_len: r=%.17g got %.17g\n", R.r, got);
+                    ++bad;
+                }
+                ++lens_checked;
+            }
             __int128 n = 0;
             for (int a = 0; a < 3; ++a)
                 n += (__int128)((int64_t)q[a] - (1024 * (int64_t)W.g[a] + 512)) * ((int64_t)q[a] - P.o[a]);
@@ -108,6 +129,39 @@ int main(int argc, char **argv)
             ++vox;
         } while (walk_next(W));
     }
-    printf("rays %ld voxels %ld ties %ld mismatches %ld\n", rays, vox, ties, bad);
-    return bad != 0 || ties == 0;
+    // fill offsets e_a = rdiv(h v_a, nv), nv = isqrt(v . v)
+    long fills = 0, fill_ties = 0;
+    for (int it = 0; it < iters; ++it) {
+        int64_t v[3];
+        const int64_t lim = it % 3 == 0 ? 4 : (int64_t)1 << std::uniform_int_distribution<int>(1, 30)(rng);
+        for (int a = 0; a < 3; ++a) v[a] = std::uniform_int_distribution<int64_t>(-lim, lim)(rng);
+        unsigned __int128 vv = 0;
+        for (int a = 0; a < 3; ++a) vv += (unsigned __int128)((__int128)v[a] * v[a]);
+        if (vv == 0) continue;
+        unsigned __int128 nv = (unsigned __int128)std::sqrt((long double)vv);
+        while (nv * nv > vv) --nv;
+        while ((nv + 1) * (nv + 1) <= vv) ++nv;
+        const double nvd = (double)(uint64_t)nv;
+        const double inv_2nv = 1.0 / (2.0 * nvd);
+        for (int k = 0; k < 8; ++k) {
+            const int64_t h = k == 0 ? 65535 : (k == 1 ? 0 : std::uniform_int_distribution<int64_t>(1, 65535)(rng));
+            for (int a = 0; a < 3; ++a) {
+                const __int128 num = (__int128)h * v[a];
+                const __int128 an = num < 0 ? -num : num;
+                const __int128 d = (__int128)(uint64_t)nv;
+                __int128 want = (2 * an + d) / (2 * d);
+                fill_ties += (2 * an + d) % (2 * d) == 0;
+                if (num < 0) want = -want;
+                const int32_t got = fill_offset((double)h * (double)v[a], nvd + 0.5, inv_2nv);
+                if ((__int128)got != want) {
+                    if (bad < 5) printf("fill_offset: h %lld v %lld nv %.17g\n", (long long)h, (long long)v[a], nvd);
+                    ++bad;
+                }
+                ++fills;
+            }
+        }
+    }
+    printf("rays %ld voxels %ld ties %ld band lengths %ld fill offsets %ld (ties %ld) mismatches %ld\n", rays, vox,
+           ties, lens_checked, fills, fill_ties, bad);
+    return bad != 0 || ties == 0 || fill_ties == 0 || lens_checked == 0;
 }
