@@ -465,7 +465,7 @@ __device__ __forceinline__ MapDev uniform_map(const MapDev &m)
 // weights in LDS.
 // At most 96 VGPRs: five waves per SIMD, the most this kernel holds without
 // spilling.
-template <int kTileBlock>
+template <int kTileBlock, bool kStats>
 __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_tile(BatchArrays B)
 {
     extern __shared__ uint64_t s_keys[];  // G * tvox keys, then the cached tile: tvox sdf, tvox w
@@ -594,7 +594,7 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                     atomicMin(lds_pointer(V.lv), (unsigned long long)band_key(V.n, rh, R.inv_r2, taud, ihi, ilo));
                     ++visits;
                 } while (box_walk_next(V));
-                if (H.want_stats && visits) atomicAdd(&s_vis[r], visits);
+                if (kStats && visits) atomicAdd(&s_vis[r], visits);
             }
             __syncthreads();
             if (cached) {
@@ -626,7 +626,7 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                         c_w[v] = (int16_t)vw;
                     }
                 }
-                if (H.want_stats)
+                if (kStats)
                     for (int r = 0; r < ng; ++r)
                         if (upd[r]) atomicAdd(&s_upd[r], upd[r]);
             } else {
@@ -644,13 +644,13 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                     const int64_t row = ((int64_t)sx * MD.dims[1] + sy) * MD.dims[2];
                     updated += merge_run_direct(&s_keys[(size_t)rb * tvox + v0], MD, row, rz0);
                 }
-                if (H.want_stats && updated) atomicAdd(&s_upd[rb], updated);
+                if (kStats && updated) atomicAdd(&s_upd[rb], updated);
             }
             __syncthreads();
             if (threadIdx.x < (uint32_t)ng) {
                 const uint32_t k = (uint32_t)s_list[j0 + threadIdx.x] * H.gtiles + g;  // sequence slot, tile
                 B.counts[k] = 0;  // ready for the next batch
-                if (H.want_stats) {
+                if (kStats) {
                     B.tile_vis[k] = s_vis[threadIdx.x];
                     B.tile_upd[k] = s_upd[threadIdx.x];
                 }
@@ -763,10 +763,16 @@ hipError_t launch_batch(const BatchArrays &B, const LaunchCaps &caps, hipStream_
     launch_bin_any(true, bins, caps.bin_block, B, none, stream);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev_binned && (e = hipEventRecord(ev_binned, stream)) != hipSuccess) return e;
-    if (caps.tile_block == 512)
-        hipLaunchKernelGGL(k_tile<512>, dim3((uint32_t)caps.tile_grid), dim3(512), caps.tile_lds, stream, B);
-    else
-        hipLaunchKernelGGL(k_tile<256>, dim3((uint32_t)caps.tile_grid), dim3(256), caps.tile_lds, stream, B);
+    // the per-scan counts are a template switch: without them the walk and
+    // the merges carry no counters
+    const dim3 tg((uint32_t)caps.tile_grid);
+    if (caps.tile_block == 512) {
+        if (caps.stats) hipLaunchKernelGGL((k_tile<512, true>), tg, dim3(512), caps.tile_lds, stream, B);
+        else hipLaunchKernelGGL((k_tile<512, false>), tg, dim3(512), caps.tile_lds, stream, B);
+    } else {
+        if (caps.stats) hipLaunchKernelGGL((k_tile<256, true>), tg, dim3(256), caps.tile_lds, stream, B);
+        else hipLaunchKernelGGL((k_tile<256, false>), tg, dim3(256), caps.tile_lds, stream, B);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev_tiles && (e = hipEventRecord(ev_tiles, stream)) != hipSuccess) return e;
     if (caps.stats) hipLaunchKernelGGL(k_stats, dim3(caps.scans > 0 ? caps.scans : 1u), dim3(256), 0, stream, B);
