@@ -341,7 +341,7 @@ __global__ __launch_bounds__(kAllocBlock) void k_alloc(BatchArrays B)
 // registers (the stored int16 values, sign-extended once).
 __device__ __forceinline__ void merge_one(int32_t &sdf, int32_t &w, uint64_t key, int32_t w_max)
 {
-    const int32_t v = (int16_t)(uint16_t)(key & 0xffffu);
+    const int32_t v = tile_key_sdf(key);
     sdf = rdiv_small(__mul24(sdf, w) + v, w + 1);  // |sdf|, w < 2^15: a 24-bit product
     w = w + 1 < w_max ? w + 1 : w_max;
 }
@@ -591,7 +591,7 @@ __global__ __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(5)))
                 const uint32_t ihi = i >> 16, ilo = i << 16;
                 uint32_t visits = 0;
                 do {
-                    atomicMin(lds_pointer(V.lv), (unsigned long long)band_key(V.n, rh, R.inv_r2, taud, ihi, ilo));
+                    atomicMin(lds_pointer(V.lv), (unsigned long long)tile_key(V.n, rh, R.inv_r2, taud, ihi, ilo));
                     ++visits;
                 } while (box_walk_next(V));
                 if (kStats && visits) atomicAdd(&s_vis[r], visits);

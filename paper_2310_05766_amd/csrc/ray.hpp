@@ -222,6 +222,29 @@ __device__ __forceinline__ uint64_t band_key(double n, double rh, double inv_r2,
     return (uint64_t)(as << 16 | ihi) << 32 | lo;
 }
 
+// The tile pass's key of a band walk voxel, ordered like band_key: |s| << 48
+// | i << 16 | sign, with the sign of s (that of n) in bit 0 instead of s's
+// low 16 bits. A point meets a voxel once per scan, so keys of equal |s|
+// and i never meet and the low bits decide nothing; the sign is n's sign
+// bit (n is an integer-valued double; -0 only with |s| = 0).
+__device__ __forceinline__ uint64_t tile_key(double n, double rh, double inv_r2, double taud, uint32_t ihi,
+                                             uint32_t ilo)
+{
+    const double k = floor(__fma_rn(2.0, fabs(n), rh) * inv_r2);
+    const uint32_t as = (uint32_t)min_nonan(k, taud);
+    uint64_t nb;
+    __builtin_memcpy(&nb, &n, sizeof(nb));  // n's bits (a register move)
+    const uint32_t lo = ilo | (uint32_t)(nb >> 63);
+    return (uint64_t)(as << 16 | ihi) << 32 | lo;
+}
+
+// s of a tile_key: |s| with the sign of bit 0.
+__device__ __forceinline__ int32_t tile_key_sdf(uint64_t key)
+{
+    const int32_t as = (int32_t)(key >> 48);
+    return (key & 1u) ? -as : as;
+}
+
 // Vertical interpolation (Sec. VI, Eq. (3)/(4)) of a band voxel c, in
 // float64 with no 64-bit integer product or correction step.
 //

@@ -8,7 +8,8 @@
 // exact ties (2|n| + r divisible by 2r) are frequent. The hardware
 // reciprocal estimate is replaced by 1/d scaled by (1 + p), p running over
 // errors up to 2^-14, which the Newton steps absorb. The interpolation's
-// float64 forms are checked the same way: band_len against rdiv((c - o) .
+// float64 forms are checked the same way (and the tile pass's tile_key,
+// which carries s's sign in bit 0): band_len against rdiv((c - o) .
 // D, r) at every band voxel of rays with r < 2^30, and fill_offset against
 // rdiv(h v_a, nv) for random and tiny (tie-prone) vectors v. The test
 // driver defines RAY_HPP (a copy of ray.hpp whose one inline-asm minimum is
@@ -119,8 +120,11 @@ int main(int argc, char **argv)
             if (n < 0) s = -s;
             const uint64_t want = pack_key(s, i);
             const bool ok_band = (double)n == W.n && band_key(W.n, R.r + 0.5, R.inv_r2, (double)P.tau, i >> 16, i << 16) == want;
+            // the tile pass's key: the same |s| and i above bit 16, s's sign in bit 0
+            const uint64_t tk = tile_key(W.n, R.r + 0.5, R.inv_r2, (double)P.tau, i >> 16, i << 16);
+            const bool ok_tile = (tk >> 16) == (want >> 16) && (tk & 0xfffeu) == 0 && tile_key_sdf(tk) == s;
             const bool ok_sdf = pack_key(voxel_sdf(W.n, R, P.tau), i) == want;
-            if (!ok_band || !ok_sdf) {
+            if (!ok_band || !ok_sdf || !ok_tile) {
                 if (bad < 5)
                     printf("mismatch: r=%llu tau=%d n=%.17g perturbation %g\n", (unsigned long long)(uint64_t)R.r,
                            P.tau, (double)n, g_pert);
