@@ -21,6 +21,7 @@ Prints ONE JSON line. Extra legs (all outside the timed region):
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -572,6 +573,14 @@ def main():
 
     import numpy as np
     import torch
+
+    # Python's cyclic garbage collector stays paused for the whole run, as
+    # timeit pauses it: with torch and the synthetic scans loaded, a full
+    # collection takes tens of milliseconds, longer than a whole timed window
+    # of batched steps, and would land in one now and then. Reference
+    # counting still frees everything the run drops.
+    gc.collect()
+    gc.disable()
 
     if args.copy_calibration:
         n = 256 * 1024 * 1024
